@@ -1,0 +1,303 @@
+"""Plain serial FP64 oracle for the spacetree PIC hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; never by the product library.  It
+shares no code with the GPU path.  The arithmetic lives in ``pic_oracle.c``
+(serial C, ``-O2 -ffp-contract=off``); this module marshals numpy arrays and
+adds the FP64 support pieces that sit outside the hot path (periodic Poisson
+solve and the vertex field), which the physics pins need.
+
+Paper sections followed (see the C file header for the readings):
+  Sec. 2   PIC cycle: deposit rho = sum R(x_i), solve, E = -grad V,
+           gather E_i = R^T(x_i) E, push.
+  Sec. 3   k=3 spacetree, dual grid, Peano ordering of the storage.
+  Sec. 4.1 PIT: each particle held by the leaf covering it (Theorem 1).
+  Sec. 4.2 PIDT: each particle held by the vertex whose dual cell covers it
+           (Theorem 2).
+  App. A   Langmuir-wave units and the Bohm-Gross relation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "_pic_oracle.so")
+
+PIT, PIDT = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def load(path: str):
+    """Load a compiled oracle library and declare its signatures."""
+    L = C.CDLL(path)
+    _declare(L)
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = load(_LIB)
+    return _lib
+
+
+def _declare(L):
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    L.orc_tree_new.restype = vp
+    L.orc_tree_new.argtypes = [i32, i32, vp]
+    L.orc_tree_free.argtypes = [vp]
+    L.orc_tree_sizes.argtypes = [vp, vp]
+    L.orc_tree_leaves.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_tree_vertices.argtypes = [vp, vp]
+    L.orc_tree_pidt.argtypes = [vp, vp, vp, vp, vp]
+    L.orc_peano.restype = C.c_uint64
+    L.orc_peano.argtypes = [i32, i32, vp]
+    L.orc_locate.restype = i32
+    L.orc_locate.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.orc_weights.restype = i32
+    L.orc_weights.argtypes = [vp, i64, vp, vp, vp]
+    L.orc_gather_push.restype = i32
+    L.orc_gather_push.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, vp, vp, i32]
+    L.orc_rebin.restype = i32
+    L.orc_rebin.argtypes = [i64, i64, vp, vp, vp, vp]
+    L.orc_deposit.restype = i32
+    L.orc_deposit.argtypes = [vp, i64, vp, vp, dbl, vp]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def peano(dim: int, level: int, coords) -> int:
+    """Peano index of the level-``level`` cell with integer ``coords``."""
+    c = np.zeros(3, np.int64)
+    c[:dim] = coords
+    return int(lib().orc_peano(dim, level, _p(c)))
+
+
+class OracleTree:
+    """The oracle's own spacetree, rebuilt from the refine masks."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        self.dim = spec.dim
+        self.L = spec.max_level
+        masks = spec.masks_concat()
+        if masks.size == 0:
+            masks = np.zeros(1, np.uint8)
+        self._masks = masks
+        self._L = lib()
+        self._h = self._L.orc_tree_new(self.dim, self.L, _p(masks))
+        if not self._h:
+            raise ValueError("oracle: unsupported tree")
+        s = np.zeros(8, np.int64)
+        self._L.orc_tree_sizes(self._h, _p(s))
+        self.n_nodes, self.n_leaves, self.n_vertices, self.n_pidt, self.S = (int(v) for v in s[:5])
+        self.n_corners = 1 << self.dim
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.orc_tree_free(h)
+            self._h = None
+
+    def n_bins(self, scheme: int) -> int:
+        return self.n_leaves if scheme == PIT else self.n_pidt
+
+    def leaves(self):
+        nl, d, nc = self.n_leaves, self.dim, self.n_corners
+        key = np.zeros(nl, np.uint64)
+        level = np.zeros(nl, np.int32)
+        coord = np.zeros((nl, d), np.int64)
+        vtx = np.zeros((nl, nc), np.int32)
+        pidt = np.zeros((nl, nc), np.int32)
+        self._L.orc_tree_leaves(self._h, _p(key), _p(level), _p(coord), _p(vtx), _p(pidt))
+        return {"key": key, "level": level, "coord": coord, "vtx": vtx, "pidt": pidt}
+
+    def vertex_positions(self) -> np.ndarray:
+        """(n_vertices, dim) int64 positions in finest-cell units (periodic)."""
+        pos = np.zeros((self.n_vertices, self.dim), np.int64)
+        self._L.orc_tree_vertices(self._h, _p(pos))
+        return pos
+
+    def vertex_positions_unit(self) -> np.ndarray:
+        """(dim, n_vertices) float64 positions in domain units."""
+        return self.vertex_positions().T.astype(np.float64) / self.S
+
+    def pidt_bins(self):
+        n, d = self.n_pidt, self.dim
+        key = np.zeros(n, np.uint64)
+        level = np.zeros(n, np.int32)
+        b = np.zeros((n, d), np.int64)
+        vid = np.zeros(n, np.int32)
+        self._L.orc_tree_pidt(self._h, _p(key), _p(level), _p(b), _p(vid))
+        return {"key": key, "level": level, "b": b, "vid": vid}
+
+    # -- per-particle operations; x, v are (dim, n) float64 --------------------
+    def locate(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        n = x.shape[1]
+        leaf = np.zeros(n, np.int32)
+        pidt = np.zeros(n, np.int32)
+        cell = np.zeros((n, self.dim), np.int64)
+        if self._L.orc_locate(self._h, n, _p(x), _p(leaf), _p(pidt), _p(cell)):
+            raise ValueError("oracle: position outside [0,1)")
+        return leaf, pidt, cell
+
+    def weights(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        n = x.shape[1]
+        w = np.zeros((n, self.n_corners))
+        vtx = np.zeros((n, self.n_corners), np.int32)
+        if self._L.orc_weights(self._h, n, _p(x), _p(w), _p(vtx)):
+            raise ValueError("oracle: position outside [0,1)")
+        return w, vtx
+
+    def gather_push(self, x, v, E, qmdt, dt, scheme=PIT):
+        """One leapfrog step; returns (x', v', E_p, new_bin) without touching inputs."""
+        x = np.array(x, np.float64, order="C", copy=True)
+        v = np.array(v, np.float64, order="C", copy=True)
+        E = np.ascontiguousarray(E, np.float64)
+        assert E.shape == (self.dim, self.n_vertices)
+        n = x.shape[1]
+        ep = np.zeros((self.dim, n))
+        bins = np.zeros(n, np.int32)
+        if self._L.orc_gather_push(self._h, n, _p(x), _p(v), _p(E), float(qmdt), float(dt),
+                                 _p(ep), _p(bins), int(scheme)):
+            raise ValueError("oracle: position outside [0,1)")
+        return x, v, ep, bins
+
+    def deposit(self, x, q=None, q_uniform=0.0):
+        x = np.ascontiguousarray(x, np.float64)
+        n = x.shape[1]
+        rho = np.zeros(self.n_vertices)
+        qa = None if q is None else np.ascontiguousarray(q, np.float64)
+        if self._L.orc_deposit(self._h, n, _p(x), _p(qa), float(q_uniform), _p(rho)):
+            raise ValueError("oracle: position outside [0,1)")
+        return rho
+
+    def bin_of(self, x, scheme):
+        leaf, pidt, _ = self.locate(x)
+        return leaf if scheme == PIT else pidt
+
+
+def rebin(new_bin, n_bins: int, old_start=None):
+    """Stable re-bin: returns (perm, new_start) with out[j] = in[perm[j]]."""
+    nb = np.ascontiguousarray(new_bin, np.int32)
+    n = nb.size
+    perm = np.zeros(n, np.int64)
+    start = np.zeros(n_bins + 1, np.int64)
+    os_ = None if old_start is None else np.ascontiguousarray(old_start, np.int64)
+    if lib().orc_rebin(n, n_bins, _p(nb), _p(os_), _p(perm), _p(start)):
+        raise ValueError("oracle: bad bins")
+    return perm, start
+
+
+def initial_sort(tree: OracleTree, x, v, q=None, scheme=PIT):
+    """Bin an unsorted particle set: returns (x, v, q, bin_start, perm)."""
+    nb = tree.bin_of(x, scheme)
+    perm, start = rebin(nb, tree.n_bins(scheme), None)
+    return x[:, perm], v[:, perm], (None if q is None else q[perm]), start, perm
+
+
+def step(tree: OracleTree, x, v, E, qmdt, dt, bin_start, scheme=PIT, q=None, q_uniform=0.0):
+    """One hot-path step: gather + push, re-bin, deposit.
+
+    Returns dict(x, v, q, bin_start, perm, Ep, new_bin, rho).
+    """
+    x1, v1, ep, nb = tree.gather_push(x, v, E, qmdt, dt, scheme)
+    perm, start = rebin(nb, tree.n_bins(scheme), bin_start)
+    x2, v2 = x1[:, perm], v1[:, perm]
+    q2 = None if q is None else q[perm]
+    rho = tree.deposit(x2, q2, q_uniform)
+    return {"x": x2, "v": v2, "q": q2, "bin_start": start, "perm": perm, "Ep": ep,
+            "new_bin": nb, "rho": rho}
+
+
+# ---------------------------------------------------------------------------
+# Support outside the hot path (regular periodic trees only): Poisson + field
+# ---------------------------------------------------------------------------
+
+def _grid(a, dim, n):
+    """Vertex array (lexicographic, axis 0 fastest) -> numpy grid indexed [axis d-1, ..., axis 0]."""
+    return a.reshape((n,) * dim)
+
+
+def poisson_periodic(rho_charge, dim: int, level: int, background: float = 1.0):
+    """Solve -Lap_h V = rho_charge/h^d + background on the periodic vertex grid.
+
+    The (2d+1)-point Laplacian is diagonalised by the DFT, whose eigenvalues
+    are sum_k (2 - 2 cos(2 pi m_k / n)) / h^2.  The mean of V is fixed to 0.
+    ``rho_charge`` is vertex charge (what the deposit returns); dividing by the
+    dual-cell volume h^d gives the density.
+    """
+    n = 3 ** level
+    h = 1.0 / n
+    dens = _grid(np.asarray(rho_charge, np.float64), dim, n) / h ** dim + background
+    f = np.fft.fftn(dens)
+    lam = np.zeros((n,) * dim)
+    m = np.arange(n)
+    eig = (2.0 - 2.0 * np.cos(2.0 * np.pi * m / n)) / (h * h)
+    for ax in range(dim):
+        shape = [1] * dim
+        shape[ax] = n
+        lam = lam + eig.reshape(shape)
+    lam.flat[0] = 1.0
+    vh = f / lam
+    vh.flat[0] = 0.0
+    return np.real(np.fft.ifftn(vh)).ravel()
+
+
+def field_from_potential(V, dim: int, level: int):
+    """E = -grad V by central differences on the periodic vertex grid; (dim, n^d)."""
+    n = 3 ** level
+    h = 1.0 / n
+    g = _grid(np.asarray(V, np.float64), dim, n)
+    E = np.zeros((dim, n ** dim))
+    for k in range(dim):
+        ax = dim - 1 - k                 # axis k of the domain is numpy axis d-1-k
+        E[k] = (-(np.roll(g, -1, axis=ax) - np.roll(g, 1, axis=ax)) / (2.0 * h)).ravel()
+    return E
+
+
+def langmuir_run(tree: OracleTree, x, v, qmdt, dt, steps, q_uniform, record=None):
+    """Free-running PIC (deposit, Poisson, field, gather, push) on a regular periodic tree.
+
+    The leapfrog starts from v^{-1/2} = v^0 - (qmdt/2) E(x^0).  ``record(step,
+    rho, V, E, x, v)`` is called after each field solve.  Returns (x, v).
+    """
+    assert tree.n_vertices == tree.S ** tree.dim, "regular trees only"
+    x = np.array(x, np.float64, copy=True)
+    v = np.array(v, np.float64, copy=True)
+    for it in range(steps + 1):
+        rho = tree.deposit(x, None, q_uniform)
+        V = poisson_periodic(rho, tree.dim, tree.L)
+        E = field_from_potential(V, tree.dim, tree.L)
+        if record is not None:
+            record(it, rho, V, E, x, v)
+        if it == steps:
+            break
+        if it == 0:
+            # half kick back in time: a zero-length step with qmdt -> -qmdt/2
+            _, v, _, _ = tree.gather_push(x, v, E, -0.5 * qmdt, 0.0, PIT)
+        x, v, _, _ = tree.gather_push(x, v, E, qmdt, dt, PIT)
+    return x, v

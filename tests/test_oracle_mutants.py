@@ -1,0 +1,108 @@
+"""Mutation check of the oracle pins.
+
+Each mutant is a copy of the oracle's C source with one plausible slip planted
+(a flipped sign, a dropped term, a swapped index or operand, a wrong tie
+rule).  The copy is compiled on the CPU into a temporary library and the pins
+of ``test_oracle_pins.py`` are run against it: at least one pin must fail for
+every mutant.  This shows that the pins fix the oracle, rather than the
+oracle fixing itself.
+"""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+import test_oracle_pins as P
+import workloads as W
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "pic_oracle.c")
+
+MUTANTS = {
+    "peano_parity_of_own_axis": ("int64_t e = (others % 2) ? 2 - digit : digit;",
+                                 "int64_t e = (seen[k] % 2) ? 2 - digit : digit;"),
+    "peano_never_complements": ("int64_t e = (others % 2) ? 2 - digit : digit;",
+                                "int64_t e = digit;"),
+    "child_slot_axes_swapped": ("slot += ((o->I[k] / p3) % 3) * m; m *= 3;",
+                                "slot = slot * 3 + ((o->I[k] / p3) % 3); m *= 3;"),
+    "owner_ties_round_down": ("if (2.0 * off >= (double)o->s) c |= 1 << k;",
+                              "if (2.0 * off > (double)o->s) c |= 1 << k;"),
+    "weights_f_g_swapped": ("double wc = (c & 1) ? f[0] : g[0];",
+                            "double wc = (c & 1) ? g[0] : f[0];"),
+    "weights_drop_axis1": ("for (int k = 1; k < t->dim; ++k) wc = wc *",
+                           "for (int k = 2; k < t->dim; ++k) wc = wc *"),
+    "gather_drops_corner1": ("for (int c = 1; c < nc; ++c) e = e + w[c] * Ej[vt[c]];",
+                             "for (int c = 2; c < nc; ++c) e = e + w[c] * Ej[vt[c]];"),
+    "gather_wrong_component": ("const double *Ej = E + (int64_t)j * t->n_vtx;",
+                               "const double *Ej = E;"),
+    "push_kick_sign": ("double vj = v[j * n + p] + qmdt * e;",
+                       "double vj = v[j * n + p] - qmdt * e;"),
+    "push_drift_old_velocity": ("double xj = x[j * n + p] + vj * dt;",
+                                "double xj = x[j * n + p] + v[j * n + p] * dt;"),
+    "wrap_keeps_one": ("if (xj == 1.0) xj = 0.0;", ""),
+    "rebin_arrivals_first": ("fill_stay[b] = acc;\n        fill_move[b] = acc + cnt_stay[b];",
+                             "fill_move[b] = acc;\n        fill_stay[b] = acc + cnt_move[b];"),
+    "deposit_corner_transposed": ("double term = qp * w[c];", "double term = qp * w[c ^ 1];"),
+    "pidt_key_unshifted": ("J[k] = (b[k] * s + (t->S - 1) / 2) % t->S;",
+                           "J[k] = (b[k] * s) % t->S;"),
+    "leaf_key_span_one_axis": ("uint64_t span = (uint64_t)ipow3(t->dim * (t->L - n->level));",
+                               "uint64_t span = (uint64_t)ipow3(t->L - n->level);"),
+    "vertex_order_axis1_fastest": ("for (int k = 0; k < dim; ++k) { r += a[k] * m; m *= n; }",
+                                   "for (int k = dim - 1; k >= 0; --k) { r += a[k] * m; m *= n; }"),
+}
+
+# fast pins, cheapest first; a mutant must make at least one of them fail
+PINS = [
+    lambda: P.test_peano_matches_textbook_level1_order(),
+    lambda: P.test_peano_is_a_face_continuous_bijection(2, 2),
+    lambda: P.test_peano_prefix_property(2, 1),
+    lambda: P.test_tree_tables_match_geometry(W.disc_tree(2, 2, 4)),
+    lambda: P.test_dual_cells_nest_along_the_curve(2, 2),
+    lambda: P.test_particle_on_a_vertex_sits_entirely_there(),
+    lambda: P.test_push_kicks_against_the_field_for_negative_charge(),
+    lambda: P.test_wrap_never_returns_one(),
+    lambda: P.test_weights_exact_and_partition_of_unity(W.disc_tree(2, 2, 4)),
+    lambda: P.test_gather_reproduces_constant_and_linear_fields(),
+    lambda: P.test_deposit_exact_small_and_adjoint_to_gather(),
+    lambda: P.test_free_streaming_matches_closed_form(),
+    lambda: P.test_locate_matches_brute_force(W.disc_tree(2, 2, 4)),
+    lambda: P.test_step_satisfies_theorems_and_order("small_adaptive", 0),
+    lambda: P.test_step_satisfies_theorems_and_order("small_adaptive", 1),
+]
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    with tempfile.TemporaryDirectory() as d:
+        yield d
+
+
+def _compile(src_text, out):
+    c = out + ".c"
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", out, c, "-lm"])
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, workdir):
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    so = os.path.join(workdir, f"mut_{name}.so")
+    _compile(src.replace(old, new), so)
+    saved = oracle._lib
+    oracle._lib = oracle.load(so)
+    caught = None
+    try:
+        for i, pin in enumerate(PINS):
+            try:
+                pin()
+            except (AssertionError, ValueError) as e:
+                caught = (i, type(e).__name__)
+                break
+    finally:
+        oracle._lib = saved
+    assert caught is not None, f"no pin catches mutant {name}"
