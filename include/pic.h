@@ -1,0 +1,286 @@
+/*
+ * pic.h -- C ABI of the MI355X spacetree particle-in-cell hot path.
+ *
+ * One time step of the particle side of a particle-in-cell (PIC) cycle on a
+ * k = 3 spacetree (paper "Two Particle-in-Grid Realisations on Spacetrees",
+ * Sec. 2 for the cycle, Sec. 3 for the tree, Sec. 4 for the particle
+ * stores), split into three calls that run on one GPU stream:
+ *
+ *   pic_gather_push  field gather E_i = R^T(x_i) E and leapfrog push, and the
+ *                    new bin of every particle (leaf for PIT, dual cell for
+ *                    PIDT);
+ *   pic_rebin        stable reorder of the particle arrays into their new
+ *                    bins (Theorems 1 and 2: afterwards every particle is
+ *                    stored in the leaf / dual cell that covers it);
+ *   pic_deposit      charge deposit rho = sum_i R(x_i) on the vertices.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named *_dev are device pointers, owned by the caller, which
+ *    must keep them alive until the stream has finished the call.  Other
+ *    pointers are host pointers, read during the call only.
+ *  - `stream` is a hipStream_t passed as void*.  Every call only enqueues
+ *    work on it (no host synchronisation) unless stated otherwise; results
+ *    are deterministic: the same inputs give bit-identical outputs.
+ *  - The library allocates no device memory.  Tree tables live in a caller
+ *    buffer (pic_tree_upload); temporary storage is a caller scratch buffer
+ *    of pic_scratch_bytes() bytes.
+ *  - Errors: calls return pic_status; nothing throws or aborts.  Argument
+ *    errors are detected on the host before anything is enqueued.  Data
+ *    errors found on the device (non-finite or out-of-box coordinates) set a
+ *    sticky bit in a status word kept in the tree buffer; every kernel keeps
+ *    its indices in range regardless, so the stream stays valid, and
+ *    pic_status_sync() reports and clears the word.
+ *  - Positions are in the periodic unit box [0,1)^d.  Particle bins are
+ *    uint32 ranks in ascending space-filling-curve key order (see
+ *    pic_tree_leaf_table); segment offsets `bin_start` are int64.
+ *  - Particle counts must stay below 2^31 per call.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pic_status;
+#define PIC_OK 0
+#define PIC_E_ARG 1        /* bad argument: null pointer, size, enum value */
+#define PIC_E_SCRATCH 2    /* scratch buffer smaller than pic_scratch_bytes() */
+#define PIC_E_CAPACITY 3   /* an output or tree buffer is too small */
+#define PIC_E_NONFINITE 4  /* device: a position or velocity was NaN/Inf */
+#define PIC_E_TREE 5       /* malformed tree description */
+#define PIC_E_HIP 6        /* a HIP runtime call failed */
+#define PIC_E_RANGE 7      /* device: a position lay outside [0,1), or a bin outside the tree */
+#define PIC_E_STATE 8      /* call order violated (e.g. tree not uploaded) */
+
+/* Particle storage schemes (paper Sec. 4.1 and Sec. 4.2). */
+#define PIC_PIT 0          /* particle in tree: bin = leaf covering x (Theorem 1) */
+#define PIC_PIDT 1         /* particle in dual tree: bin = vertex of that leaf whose
+                              dual cell covers x (Theorem 2) */
+
+/* Arithmetic forms. */
+#define PIC_F64 0          /* x, v in FP64 domain units */
+#define PIC_F32_OFFSET 1   /* FP32 offsets within the leaf, FP32 velocity in cells/step */
+
+typedef struct pic_tree pic_tree;   /* opaque host object */
+
+/* ------------------------------------------------------------------ tree */
+
+/*
+ * Build the host description of a forest of `n_inst` spacetrees of the same
+ * dimension over the periodic unit box (paper Sec. 3: root = unit box, a
+ * refined cell has 3^d children, leaves are unrefined cells; Sec. 3.2 dual
+ * grid).  A single tree is a forest of one.
+ *
+ *   dim        2 or 3.
+ *   max_level  host, n_inst entries: deepest level L_i of instance i
+ *              (0 <= L_i, dim*L_i <= 36).
+ *   masks      host: for each instance in turn, for each level l < L_i, a
+ *              uint8 array of (3^l)^dim flags in lexicographic order (axis
+ *              0 fastest); 1 = the level-l cell is refined.  Flags of cells
+ *              whose parent is unrefined are ignored.
+ *   out        receives the new object (free with pic_tree_destroy).
+ *
+ * Errors: PIC_E_ARG for bad sizes or null pointers, PIC_E_TREE if a forest
+ * would exceed 2^31 leaves, vertices or nodes.
+ */
+pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level,
+                           const uint8_t *masks, pic_tree **out);
+
+void pic_tree_destroy(pic_tree *tree);
+
+typedef struct {
+    int32_t dim, n_inst;
+    int32_t regular;          /* 1 if every instance is uniformly refined */
+    int32_t max_level;        /* largest L_i */
+    int64_t n_leaves;         /* PIT bins over the forest */
+    int64_t n_vertices;       /* distinct leaf-corner positions over the forest */
+    int64_t n_pidt;           /* PIDT bins over the forest */
+    int64_t n_nodes;          /* descent-table nodes */
+    int64_t device_bytes;     /* size of the buffer pic_tree_upload needs */
+} pic_tree_info;
+
+pic_status pic_tree_get_info(const pic_tree *tree, pic_tree_info *info);
+
+typedef struct {
+    int32_t max_level;        /* L_i */
+    int32_t regular;
+    int64_t leaf_offset, n_leaves;     /* forest-wide leaf ranks of this instance */
+    int64_t vertex_offset, n_vertices; /* forest-wide vertex ids */
+    int64_t pidt_offset, n_pidt;       /* forest-wide PIDT ranks */
+} pic_instance_info;
+
+pic_status pic_tree_get_instance(const pic_tree *tree, int32_t inst, pic_instance_info *info);
+
+/*
+ * Host copies of the tables, for checking and for building fields.  Every
+ * output pointer may be NULL.  Sizes: n_leaves (key, level), n_leaves*dim
+ * (coord), n_leaves*2^dim (vtx, pidt), n_vertices*dim (pos), n_pidt
+ * (pidt_key, pidt_level), n_pidt*dim (pidt_b).
+ *   key    leaf key peano_l(a) * 3^(dim*(L-l)) * 64 + l; leaves are ranked by
+ *          ascending key within an instance, instances back to back.
+ *   coord  leaf coordinates at the leaf's own level.
+ *   vtx    forest-wide vertex id of corner c = sum_k b_k 2^k of each leaf.
+ *   pidt   forest-wide PIDT bin of each corner at the leaf's level.
+ *   pos    vertex position in finest-cell units of its instance; vertices
+ *          are numbered per instance in lexicographic order (axis 0 fastest).
+ *   pidt_key  peano_L(J') * 64 + l with J' = (b*s + (3^L-1)/2) mod 3^L.
+ *   pidt_b    vertex coordinates at the bin's level.
+ */
+pic_status pic_tree_leaf_table(const pic_tree *tree, uint64_t *key, int32_t *level,
+                               int64_t *coord, int32_t *vtx, int32_t *pidt);
+pic_status pic_tree_vertex_table(const pic_tree *tree, int64_t *pos);
+pic_status pic_tree_pidt_table(const pic_tree *tree, uint64_t *pidt_key, int32_t *pidt_level,
+                               int64_t *pidt_b);
+
+/*
+ * Copy the device tables into `buffer_dev` (at least info.device_bytes
+ * bytes, 256-byte aligned) and bind them to `tree`.  The buffer also holds
+ * the sticky status word, cleared here.  Enqueued on `stream`; the host
+ * tables stay owned by `tree`.
+ */
+pic_status pic_tree_upload(pic_tree *tree, void *buffer_dev, size_t bytes, void *stream);
+
+/*
+ * Return the sticky device status of `tree` (PIC_OK or the first data error
+ * code in the order NONFINITE, RANGE) and clear it.  Synchronises `stream`.
+ */
+pic_status pic_status_sync(pic_tree *tree, void *stream);
+
+const char *pic_status_string(pic_status s);
+
+/* -------------------------------------------------------------- particles */
+
+/*
+ * One particle set in structure-of-arrays form.  FP64 form: x[k], v[k]
+ * (k < dim) are n doubles each, x in [0,1) domain units, v in domain units
+ * per unit time.  FP32 form: off[k] in [0,1) is the offset inside the
+ * particle's leaf in leaf widths and u[k] the velocity in finest cells per
+ * step; the leaf itself is the particle's PIT bin.  Unused pointers may be
+ * NULL.
+ *
+ * inst_start_dev: for a forest, n_inst+1 int64 particle offsets: the
+ * particles of instance i are [inst_start[i], inst_start[i+1]), in order.
+ * NULL for a single tree.  Particles never change instance.
+ */
+typedef struct {
+    int64_t n;
+    double *x[3];
+    double *v[3];
+    float *off[3];
+    float *u[3];
+    const int64_t *inst_start_dev;
+} pic_particles;
+
+/* Per-instance push parameters for a forest: qmdt[i] = (q/m) dt and dt[i],
+   device arrays of n_inst doubles.  NULL pointers select the scalars. */
+typedef struct {
+    const double *qmdt_dev;
+    const double *dt_dev;
+} pic_push_params;
+
+/*
+ * Locate: the bin of every particle of an unsorted (or sorted) set.
+ * bin_dev receives n uint32 forest-wide bins of `scheme`.  Used to start a
+ * run from generated particles; pic_gather_push emits bins itself.
+ */
+pic_status pic_locate(const pic_tree *tree, int32_t scheme, int32_t precision,
+                      const pic_particles *p, const int64_t *bin_start_dev,
+                      uint32_t *bin_dev, void *stream);
+
+/*
+ * Gather + push (paper Sec. 2 items 3 and 4; d-linear shape functions).
+ * For every particle, in place:
+ *   E_p = sum_c w_c(x) E[vtx_c]   over the 2^d corners of the leaf holding x,
+ *   v  <- v + qmdt * E_p,  x <- x + v * dt,  x <- x - floor(x) (1.0 -> 0.0),
+ * then the particle's new bin under `scheme` is written to bin_dev.
+ *   E_dev[k]     device, n_vertices doubles: field component k per vertex.
+ *   qmdt, dt     (q/m)*dt and dt for a single tree; ignored per instance
+ *                when `params` has device arrays.
+ *   bin_start_dev  the current segment offsets of p (n_bins+1 int64); needed
+ *                by the FP32 form (its cell is implicit in the bin), NULL is
+ *                allowed for FP64.
+ *   Ep_dev       optional (NULL): dim*n doubles receiving E_p per particle.
+ * FP64 arithmetic follows a fixed operation order with no fused multiply-add,
+ * so x, v and the bins equal a serial IEEE evaluation of the same formulas.
+ */
+pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precision,
+                           pic_particles *p, const double *const *E_dev,
+                           double qmdt, double dt, const pic_push_params *params,
+                           const int64_t *bin_start_dev, uint32_t *bin_dev, double *Ep_dev,
+                           void *stream);
+
+/*
+ * Scratch bytes needed by pic_rebin / pic_deposit for n particles.
+ */
+size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_t precision);
+
+/*
+ * Re-bin (paper Sec. 4: after the move every particle is held by the grid
+ * entity covering it; Theorems 1 and 2; "bucket sort" into children).
+ * Output order: bins ascending; inside a bin first the particles that were
+ * already in it (in their old order), then the ones that arrived (in their
+ * old order).  When old_bin_start_dev is NULL the input is unsorted and every
+ * particle counts as arriving.
+ *   new_bin_dev        n uint32 bins (from pic_gather_push or pic_locate).
+ *   old_bin_start_dev  n_bins+1 int64 offsets of the input order, or NULL.
+ *   n_cols, cols_in_dev, cols_out_dev, col_bytes: columns permuted together
+ *                      (element size 4 or 8 bytes); outputs must not alias
+ *                      inputs.
+ *   new_bin_start_dev  receives n_bins+1 int64 offsets of the output.
+ */
+pic_status pic_rebin(const pic_tree *tree, int32_t scheme, int64_t n,
+                     const uint32_t *new_bin_dev, const int64_t *old_bin_start_dev,
+                     int32_t n_cols, void *const *cols_in_dev, void *const *cols_out_dev,
+                     const int32_t *col_bytes, int64_t *new_bin_start_dev,
+                     void *scratch_dev, size_t scratch_bytes, void *stream);
+
+/*
+ * Deposit (paper Sec. 2 item 1): rho_v = sum_p q_p w_v(x_p) for a sorted set
+ * (bin_start_dev from pic_rebin for the same scheme).  rho_dev receives
+ * n_vertices doubles (vertex charge, overwritten).  q_dev: per-particle
+ * charge (n doubles) or NULL for q_uniform.  No floating-point atomics: each
+ * vertex sums its contributions in a fixed order.
+ */
+pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
+                       const pic_particles *p, const int64_t *bin_start_dev,
+                       const double *q_dev, double q_uniform, double *rho_dev,
+                       void *scratch_dev, size_t scratch_bytes, void *stream);
+
+/* ------------------------------------------------------- measurement aids */
+
+/*
+ * Stream benchmark of the paper's evaluation (Sec. 5, stream-like particle
+ * throughput): every particle moves by one explicit Euler step x <- x + v dt
+ * and is reflected at the walls of the unit box (x -> -x below 0, 2 - x
+ * above 1, with v negated), with no grid.  x_dev, v_dev: dim pointers to n
+ * doubles each, updated in place.  Used to calibrate the achievable HBM
+ * bandwidth of structure-of-arrays particle streams.
+ */
+pic_status pic_stream_push(int32_t dim, int64_t n, double *const *x_dev, double *const *v_dev, double dt,
+                           void *stream);
+
+/*
+ * Kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by two HIP events recorded on its launch stream.
+ * pic_profile_read waits for the recorded events, writes up to max_entries
+ * per-kernel totals (name, launch count, summed milliseconds) to `out`
+ * (may be NULL), forgets them, and returns the number of distinct kernels.
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} pic_kernel_time;
+
+pic_status pic_profile_enable(int32_t on);
+int32_t pic_profile_read(pic_kernel_time *out, int32_t max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

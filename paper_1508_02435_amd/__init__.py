@@ -1,0 +1,311 @@
+"""MI355X spacetree particle-in-cell hot path: Python binding of libpic.so.
+
+The arithmetic runs in the HIP kernels of ``libpic.so`` (see ``include/pic.h``
+for the C ABI).  This module only marshals arguments: PyTorch provides device
+memory and the current HIP stream.  There is no CPU fallback; if the library
+or a GPU is missing the calls raise.
+
+Paper: "Two Particle-in-Grid Realisations on Spacetrees" (Sec. 2 PIC cycle,
+Sec. 3 spacetree and dual grid, Sec. 4.1 PIT, Sec. 4.2 PIDT).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _capi
+from ._capi import F32_OFFSET, F64, PIDT, PIT, PicError, check, lib
+
+__all__ = ["Tree", "PIT", "PIDT", "F64", "F32_OFFSET", "PicError", "locate", "gather_push", "rebin",
+           "deposit", "scratch_bytes", "Stepper", "lib"]
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _need(cond: bool, what: str):
+    if not cond:
+        raise ValueError(what)
+
+
+def _check_soa(t, dim: int, n: int, dtype_name: str, what: str):
+    import torch
+    _need(t is not None and t.is_cuda and t.is_contiguous(), f"{what}: contiguous device tensor expected")
+    _need(t.dim() == 2 and t.shape[0] >= dim and t.shape[1] == n, f"{what}: shape (dim, n) expected")
+    _need(t.dtype == getattr(torch, dtype_name), f"{what}: {dtype_name} expected")
+
+
+def _check_vec(t, n: int, what: str):
+    _need(t is not None and t.is_cuda and t.is_contiguous() and t.numel() >= n, f"{what}: >= {n} elements on device")
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Tree:
+    """A forest of spacetrees (one or more instances of the same dimension).
+
+    ``specs``: objects with ``dim``, ``max_level`` and ``masks_concat()``
+    (refine flags per level, lexicographic, axis 0 fastest).
+    """
+
+    def __init__(self, specs):
+        if not isinstance(specs, (list, tuple)):
+            specs = [specs]
+        dim = specs[0].dim
+        assert all(s.dim == dim for s in specs)
+        levels = np.array([s.max_level for s in specs], np.int32)
+        masks = np.concatenate([s.masks_concat() for s in specs] + [np.zeros(1, np.uint8)])
+        self._masks = np.ascontiguousarray(masks)
+        h = C.c_void_p()
+        check(lib().pic_tree_create(dim, len(specs), levels.ctypes.data_as(C.c_void_p),
+                                    self._masks.ctypes.data_as(C.c_void_p), C.byref(h)), "pic_tree_create")
+        self._h = h
+        info = _capi.TreeInfo()
+        check(lib().pic_tree_get_info(self._h, C.byref(info)), "pic_tree_get_info")
+        self.info = info
+        self.dim = info.dim
+        self.n_inst = info.n_inst
+        self.n_leaves = info.n_leaves
+        self.n_vertices = info.n_vertices
+        self.n_pidt = info.n_pidt
+        self.regular = bool(info.regular)
+        self.buffer = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().pic_tree_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def n_bins(self, scheme: int) -> int:
+        return self.n_leaves if scheme == PIT else self.n_pidt
+
+    def instance(self, i: int) -> _capi.InstanceInfo:
+        ii = _capi.InstanceInfo()
+        check(lib().pic_tree_get_instance(self._h, i, C.byref(ii)), "pic_tree_get_instance")
+        return ii
+
+    # host tables -------------------------------------------------------------
+    def leaf_table(self):
+        nl, d, nc = self.n_leaves, self.dim, 1 << self.dim
+        key = np.zeros(nl, np.uint64)
+        level = np.zeros(nl, np.int32)
+        coord = np.zeros((nl, d), np.int64)
+        vtx = np.zeros((nl, nc), np.int32)
+        pidt = np.zeros((nl, nc), np.int32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        check(lib().pic_tree_leaf_table(self._h, p(key), p(level), p(coord), p(vtx), p(pidt)), "leaf_table")
+        return {"key": key, "level": level, "coord": coord, "vtx": vtx, "pidt": pidt}
+
+    def vertex_table(self):
+        pos = np.zeros((self.n_vertices, self.dim), np.int64)
+        check(lib().pic_tree_vertex_table(self._h, pos.ctypes.data_as(C.c_void_p)), "vertex_table")
+        return pos
+
+    def pidt_table(self):
+        n, d = self.n_pidt, self.dim
+        key = np.zeros(n, np.uint64)
+        level = np.zeros(n, np.int32)
+        b = np.zeros((n, d), np.int64)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        check(lib().pic_tree_pidt_table(self._h, p(key), p(level), p(b)), "pidt_table")
+        return {"key": key, "level": level, "b": b}
+
+    # device ------------------------------------------------------------------
+    def upload(self, device="cuda", stream=None):
+        import torch
+        nbytes = int(self.info.device_bytes)
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self.buffer = buf
+        check(lib().pic_tree_upload(self._h, C.c_void_p(buf.data_ptr() + off), nbytes, C.c_void_p(_stream(stream))),
+              "pic_tree_upload")
+        return self
+
+    def status_sync(self, stream=None) -> int:
+        return lib().pic_status_sync(self._h, C.c_void_p(_stream(stream)))
+
+
+def _particles(n, x=None, v=None, off=None, u=None, inst_start=None) -> _capi.Particles:
+    P = _capi.Particles()
+    P.n = int(n)
+    for k in range(3):
+        P.x[k] = _ptr(x[k]) if x is not None and k < x.shape[0] else None
+        P.v[k] = _ptr(v[k]) if v is not None and k < v.shape[0] else None
+        P.off[k] = _ptr(off[k]) if off is not None and k < off.shape[0] else None
+        P.u[k] = _ptr(u[k]) if u is not None and k < u.shape[0] else None
+    P.inst_start_dev = _ptr(inst_start)
+    return P
+
+
+def _check_inst(tree, inst_start):
+    if tree.n_inst > 1:
+        _check_vec(inst_start, tree.n_inst + 1, "inst_start")
+
+
+def scratch_bytes(tree: Tree, n: int, scheme: int, precision: int = F64) -> int:
+    return int(lib().pic_scratch_bytes(tree.handle, int(n), scheme, precision))
+
+
+def locate(tree: Tree, scheme: int, x, bin_out, inst_start=None, stream=None):
+    """Bins of an (unsorted) FP64 set: x is a (dim, n) float64 device tensor."""
+    _check_soa(x, tree.dim, x.shape[1], "float64", "x")
+    _check_vec(bin_out, x.shape[1], "bin_out")
+    _check_inst(tree, inst_start)
+    P = _particles(x.shape[1], x=x, inst_start=inst_start)
+    check(lib().pic_locate(tree.handle, scheme, F64, C.byref(P), None, C.c_void_p(_ptr(bin_out)),
+                           C.c_void_p(_stream(stream))), "pic_locate")
+
+
+def gather_push(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_out, Ep=None,
+                inst_start=None, qmdt_dev=None, dt_dev=None, stream=None):
+    """In-place leapfrog step of an FP64 set; writes new bins to bin_out."""
+    n = x.shape[1]
+    _check_soa(x, tree.dim, n, "float64", "x")
+    _check_soa(v, tree.dim, n, "float64", "v")
+    _check_vec(bin_out, n, "bin_out")
+    for k in range(tree.dim):
+        _check_vec(E[k], tree.n_vertices, f"E[{k}]")
+    if Ep is not None:
+        _check_soa(Ep, tree.dim, n, "float64", "Ep")
+    _check_inst(tree, inst_start)
+    for a in (qmdt_dev, dt_dev):
+        if a is not None:
+            _check_vec(a, tree.n_inst, "per-instance parameter")
+    P = _particles(x.shape[1], x=x, v=v, inst_start=inst_start)
+    Eptr = (C.c_void_p * 3)(*[_ptr(E[k]) if k < tree.dim else None for k in range(3)])
+    pp = _capi.PushParams(_ptr(qmdt_dev), _ptr(dt_dev))
+    check(lib().pic_gather_push(tree.handle, scheme, F64, C.byref(P), Eptr, float(qmdt), float(dt),
+                                C.byref(pp), None, C.c_void_p(_ptr(bin_out)),
+                                C.c_void_p(_ptr(Ep)) if Ep is not None else None,
+                                C.c_void_p(_stream(stream))), "pic_gather_push")
+
+
+def rebin(tree: Tree, scheme: int, new_bin, old_start, cols_in: Sequence, cols_out: Sequence, new_start,
+          scratch, stream=None):
+    """Stable re-bin; permutes every column of cols_in into cols_out."""
+    n = new_bin.numel()
+    _check_vec(new_bin, n, "new_bin")
+    nb = tree.n_bins(scheme)
+    if old_start is not None:
+        _check_vec(old_start, nb + 1, "old_start")
+    _check_vec(new_start, nb + 1, "new_start")
+    _need(len(cols_in) == len(cols_out), "column lists differ in length")
+    for a, b in zip(cols_in, cols_out):
+        _check_vec(a, n, "column in")
+        _check_vec(b, n, "column out")
+        _need(a.element_size() == b.element_size(), "column widths differ")
+    nc = len(cols_in)
+    ins = (C.c_void_p * max(nc, 1))(*[_ptr(c) for c in cols_in])
+    outs = (C.c_void_p * max(nc, 1))(*[_ptr(c) for c in cols_out])
+    sizes = (C.c_int32 * max(nc, 1))(*[c.element_size() for c in cols_in])
+    check(lib().pic_rebin(tree.handle, scheme, n, C.c_void_p(_ptr(new_bin)),
+                          C.c_void_p(_ptr(old_start)) if old_start is not None else None,
+                          nc, ins, outs, sizes, C.c_void_p(_ptr(new_start)), C.c_void_p(_ptr(scratch)),
+                          scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))), "pic_rebin")
+
+
+def deposit(tree: Tree, scheme: int, x, bin_start, rho, scratch, q=None, q_uniform: float = 0.0,
+            inst_start=None, stream=None):
+    """Vertex charge of a sorted FP64 set."""
+    n = x.shape[1]
+    _check_soa(x, tree.dim, n, "float64", "x")
+    _check_vec(bin_start, tree.n_bins(scheme) + 1, "bin_start")
+    _check_vec(rho, tree.n_vertices, "rho")
+    if q is not None:
+        _check_vec(q, n, "q")
+    _check_inst(tree, inst_start)
+    P = _particles(x.shape[1], x=x, inst_start=inst_start)
+    check(lib().pic_deposit(tree.handle, scheme, F64, C.byref(P), C.c_void_p(_ptr(bin_start)),
+                            C.c_void_p(_ptr(q)) if q is not None else None, float(q_uniform),
+                            C.c_void_p(_ptr(rho)), C.c_void_p(_ptr(scratch)),
+                            scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))),
+          "pic_deposit")
+
+
+class Stepper:
+    """Device state of one particle set and the three calls of a time step.
+
+    Holds two SoA buffers (the re-bin writes into the other one), the bin
+    array, the segment offsets and one scratch buffer.  Optional per-particle
+    charge ``q`` and integer tags ``ids`` travel with the particles.
+    """
+
+    def __init__(self, tree: Tree, scheme: int, x, v, q=None, ids=None, inst_start=None, device="cuda"):
+        import torch
+        self.tree, self.scheme = tree, scheme
+        self.n = int(x.shape[1])
+        dev = torch.device(device)
+        self.x = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
+        self.v = torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev).contiguous()
+        self.q = None if q is None else torch.as_tensor(np.ascontiguousarray(q), dtype=torch.float64,
+                                                        device=dev).contiguous()
+        self.ids = None if ids is None else torch.as_tensor(np.ascontiguousarray(ids), device=dev).contiguous()
+        self.x2 = torch.empty_like(self.x)
+        self.v2 = torch.empty_like(self.v)
+        self.q2 = None if self.q is None else torch.empty_like(self.q)
+        self.ids2 = None if self.ids is None else torch.empty_like(self.ids)
+        self.bin = torch.empty(self.n, dtype=torch.int32, device=dev)
+        nb = tree.n_bins(scheme)
+        self.start = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.start2 = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.scratch = torch.empty(scratch_bytes(tree, self.n, scheme) // 8 + 1, dtype=torch.int64, device=dev)
+        self.rho = torch.zeros(tree.n_vertices, dtype=torch.float64, device=dev)
+        self.Ep = None
+        self.inst_start = inst_start
+
+    def _cols(self, a, b):
+        ins = [a[0][k] for k in range(self.tree.dim)] + [a[1][k] for k in range(self.tree.dim)]
+        outs = [b[0][k] for k in range(self.tree.dim)] + [b[1][k] for k in range(self.tree.dim)]
+        if self.q is not None:
+            ins.append(a[2]); outs.append(b[2])
+        if self.ids is not None:
+            ins.append(a[3]); outs.append(b[3])
+        return ins, outs
+
+    def _swap(self):
+        self.x, self.x2 = self.x2, self.x
+        self.v, self.v2 = self.v2, self.v
+        self.q, self.q2 = self.q2, self.q
+        self.ids, self.ids2 = self.ids2, self.ids
+        self.start, self.start2 = self.start2, self.start
+
+    def initial_sort(self):
+        locate(self.tree, self.scheme, self.x, self.bin, inst_start=self.inst_start)
+        ins, outs = self._cols((self.x, self.v, self.q, self.ids), (self.x2, self.v2, self.q2, self.ids2))
+        rebin(self.tree, self.scheme, self.bin, None, ins, outs, self.start2, self.scratch)
+        self._swap()
+
+    def gather_push(self, E, qmdt, dt, want_Ep=False, **kw):
+        import torch
+        if want_Ep and self.Ep is None:
+            self.Ep = torch.empty_like(self.x)
+        gather_push(self.tree, self.scheme, self.x, self.v, E, qmdt, dt, self.bin,
+                    Ep=self.Ep if want_Ep else None, inst_start=self.inst_start, **kw)
+
+    def rebin(self):
+        ins, outs = self._cols((self.x, self.v, self.q, self.ids), (self.x2, self.v2, self.q2, self.ids2))
+        rebin(self.tree, self.scheme, self.bin, self.start, ins, outs, self.start2, self.scratch)
+        self._swap()
+
+    def deposit(self, q_uniform=0.0):
+        deposit(self.tree, self.scheme, self.x, self.start, self.rho, self.scratch, q=self.q,
+                q_uniform=q_uniform, inst_start=self.inst_start)
+
+    def step(self, E, qmdt, dt, q_uniform=0.0, **kw):
+        self.gather_push(E, qmdt, dt, **kw)
+        self.rebin()
+        self.deposit(q_uniform)

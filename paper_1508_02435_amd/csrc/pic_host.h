@@ -1,0 +1,102 @@
+// pic_host.h -- host-side objects of the library (not part of the C ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_internal.h"
+
+namespace pic {
+
+// One instance, built on the host (forest-local indices).
+struct HostInst {
+    int L = 0;
+    int64_t S = 1;
+    int regular = 0;
+    std::vector<int32_t> node_child;   // compacted descent table (local indices)
+    std::vector<uint32_t> uni_base;    // local leaf rank
+    std::vector<uint32_t> uni_meta;
+    std::vector<uint64_t> leaf_key;
+    std::vector<uint8_t> leaf_level;
+    std::vector<uint32_t> leaf_coord;  // n_leaves * dim
+    std::vector<int32_t> leaf_vtx;     // local vertex ids
+    std::vector<int32_t> leaf_pidt;    // local PIDT bins
+    std::vector<int64_t> vtx_lin;      // sorted lexicographic positions
+    std::vector<uint64_t> pidt_key;
+    std::vector<uint8_t> pidt_level;
+    std::vector<uint32_t> pidt_b;      // n_pidt * dim
+    std::vector<int32_t> pidt_vtx;
+};
+
+pic_status build_instance(int dim, int L, const uint8_t *masks, HostInst &out);
+void build_incidence(int dim, const HostInst &h, int32_t leaf_off, int32_t pidt_off,
+                     std::vector<std::vector<int32_t>> &vinc_rows,
+                     std::vector<std::vector<int32_t>> &vpinc_rows);
+uint64_t host_peano(int dim, const uint32_t *a, int nd);
+
+}  // namespace pic
+
+// The opaque tree object of the C ABI.
+struct pic_tree {
+    int32_t dim = 0, n_inst = 0, all_regular = 1, max_level = 0;
+    std::vector<pic::HostInst> inst;
+    std::vector<int64_t> leaf_off, vtx_off, pidt_off, node_off;  // n_inst + 1 each
+    std::vector<uint8_t> image;        // host copy of the device image
+    int64_t device_bytes = 0;
+    // byte offsets of the tables inside the image
+    int64_t o_status = 0, o_inst = 0, o_node = 0, o_ubase = 0, o_umeta = 0, o_llev = 0, o_lvtx = 0,
+            o_lpidt = 0, o_plev = 0, o_linst = 0, o_pinst = 0, o_vinst = 0, o_vptr = 0, o_vinc = 0,
+            o_vpptr = 0, o_vpinc = 0;
+    int64_t n_nodes = 0, n_vinc = 0, n_vpinc = 0;
+    void *dev = nullptr;               // bound device buffer (caller-owned)
+    pic::DevTree dt{};                 // device view, valid once uploaded
+    pic::DevInst inst0{};              // instance 0 (passed by value for single trees)
+};
+
+namespace pic {
+
+// Records HIP events around a kernel launch when profiling is enabled.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    void *a_;
+};
+
+#define PIC_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                     \
+    do {                                                                           \
+        ::pic::ProfScope pic_prof_scope_(NAME, STREAM);                            \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);         \
+    } while (0)
+
+// kernel launchers (pic_kernels.hip); all enqueue on `stream`
+struct Cols {
+    int32_t n;
+    const void *in[16];
+    void *out[16];
+    int32_t bytes[16];
+};
+
+hipError_t launch_locate(const pic_tree *t, int scheme, const pic_particles *p, uint32_t *bin,
+                         hipStream_t s);
+hipError_t launch_gather_push(const pic_tree *t, int scheme, pic_particles *p, const double *const *E,
+                              double qmdt, double dt, const pic_push_params *pp, uint32_t *bin,
+                              double *Ep, hipStream_t s);
+hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t *new_bin,
+                        const int64_t *old_start, const Cols &cols, int64_t *new_start,
+                        void *scratch, size_t scratch_bytes, hipStream_t s);
+size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme);
+hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
+                          const int64_t *bin_start, const double *q, double q_uniform, double *rho,
+                          void *scratch, size_t scratch_bytes, hipStream_t s);
+size_t deposit_scratch_bytes(const pic_tree *t, int scheme);
+hipError_t launch_status_clear(const pic_tree *t, hipStream_t s);
+hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *const *v, double dt, hipStream_t s);
+
+}  // namespace pic

@@ -1,0 +1,247 @@
+"""GPU parity of the HIP hot path against the oracle (FP64 form).
+
+Bar: bins, order and bin offsets bit-exact; x, v and the gathered field
+bit-exact (the kernels follow the same IEEE operation sequence without
+contraction); vertex charge within 1e-12 relative per vertex (all terms of a
+vertex share one sign, so any summation order stays within (n-1) u).
+Every call goes through libpic.so's C ABI via the Python binding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1508_02435_amd as pic  # noqa: E402
+
+CASES = [("config1", 0), ("config1", 1), ("small_adaptive", 0), ("small_adaptive", 1),
+         ("small_3d", 0), ("small_3d", 1), ("small_3d_adaptive", 0), ("small_3d_adaptive", 1)]
+RHO_TOL = 1e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda")
+
+
+def _tree(spec):
+    return pic.Tree(spec).upload()
+
+
+def _field(o, wl, rng, kind):
+    if kind == "random":
+        # a few cells of displacement per step: tunnelling in every direction
+        scale = 3.0 * wl.h / (wl.dt * wl.dt)
+        return W.random_field(rng, wl.dim, o.n_vertices, scale)
+    return wl.field(o.vertex_positions_unit())
+
+
+def _check_rho(rho_gpu, rho_orc):
+    err = np.abs(rho_gpu - rho_orc)
+    ok = err <= RHO_TOL * np.abs(rho_orc) + 1e-300
+    assert ok.all(), (err.max(), np.abs(rho_orc).max(), int((~ok).sum()))
+
+
+@pytest.mark.parametrize("name,scheme", CASES)
+def test_locate_matches_oracle(name, scheme):
+    dev = _dev()
+    wl = W.by_name(name)
+    o = oracle.OracleTree(wl.tree)
+    t = _tree(wl.tree)
+    x = torch.tensor(wl.x, dtype=torch.float64, device=dev)
+    b = torch.empty(wl.n, dtype=torch.int32, device=dev)
+    pic.locate(t, scheme, x, b)
+    torch.cuda.synchronize()
+    assert np.array_equal(b.cpu().numpy(), o.bin_of(wl.x, scheme))
+    assert t.status_sync() == 0
+
+
+@pytest.mark.parametrize("kind", ["random", "physical"])
+@pytest.mark.parametrize("name,scheme", CASES)
+def test_step_matches_oracle(name, scheme, kind):
+    """Initial sort, then three teacher-forced steps: every output compared."""
+    dev = _dev()
+    wl = W.by_name(name)
+    o = oracle.OracleTree(wl.tree)
+    t = _tree(wl.tree)
+    rng = np.random.default_rng(99)
+    ids = np.arange(wl.n, dtype=np.int64)
+    st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, ids=ids, device=dev)
+    st.initial_sort()
+    # oracle initial sort
+    nb0 = o.bin_of(wl.x, scheme)
+    perm, start = oracle.rebin(nb0, o.n_bins(scheme), None)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.ids.cpu().numpy(), perm)
+    assert np.array_equal(st.start.cpu().numpy(), start)
+    x, v = wl.x[:, perm], wl.v[:, perm]
+    q = None if wl.q is None else wl.q[perm]
+    for it in range(3):
+        E = _field(o, wl, rng, kind)
+        Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+        qmdt, dt = wl.qm * wl.dt, wl.dt
+        # teacher forcing: the GPU starts every step from the oracle's state
+        st.x.copy_(torch.from_numpy(x))
+        st.v.copy_(torch.from_numpy(v))
+        st.gather_push(Ed, qmdt, dt, want_Ep=True)
+        x1, v1, ep, nb = o.gather_push(x, v, E, qmdt, dt, scheme)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.x.cpu().numpy(), x1), f"x differs at step {it}"
+        assert np.array_equal(st.v.cpu().numpy(), v1), f"v differs at step {it}"
+        assert np.array_equal(st.Ep.cpu().numpy(), ep), f"E_p differs at step {it}"
+        assert np.array_equal(st.bin.cpu().numpy(), nb), f"bins differ at step {it}"
+        ids_before = st.ids.cpu().numpy()
+        st.rebin()
+        perm, start2 = oracle.rebin(nb, o.n_bins(scheme), start)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.start.cpu().numpy(), start2), f"bin_start differs at step {it}"
+        assert np.array_equal(st.ids.cpu().numpy(), ids_before[perm]), f"order differs at step {it}"
+        x, v, start = x1[:, perm], v1[:, perm], start2
+        q = None if q is None else q[perm]
+        assert np.array_equal(st.x.cpu().numpy(), x)
+        st.deposit(wl.q_uniform)
+        rho = o.deposit(x, q, wl.q_uniform)
+        torch.cuda.synchronize()
+        _check_rho(st.rho.cpu().numpy(), rho)
+    assert t.status_sync() == 0
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_deposit_is_bitwise_deterministic(scheme):
+    dev = _dev()
+    wl = W.config1()
+    t = _tree(wl.tree)
+    outs = []
+    for _ in range(2):
+        st = pic.Stepper(t, scheme, wl.x, wl.v, device=dev)
+        st.initial_sort()
+        st.deposit(wl.q_uniform)
+        outs.append(st.rho.cpu().numpy().copy())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+
+
+def _synthetic(n, dim, rng, kind):
+    if kind == "one_cell":              # every particle in one cell: one segment over many tiles
+        x = 0.4 + 0.001 * rng.random((dim, n))
+    elif kind == "faces":               # on cell faces, half cells and the box edge
+        g = np.array([0.0, np.nextafter(1.0, 0.0), 1 / 3, 2 / 9, 0.5, 1 / 6, np.nextafter(1 / 3, 0.0)])
+        x = g[rng.integers(0, g.size, (dim, n))]
+    else:
+        x = rng.random((dim, n))
+    return x, rng.standard_normal((dim, n)) * 0.05
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 4095, 4096, 4097, 3 * 4096 + 17])
+@pytest.mark.parametrize("kind", ["uniform", "one_cell", "faces"])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_edge_sizes_and_positions(n, kind, scheme):
+    dev = _dev()
+    rng = np.random.default_rng(n + 7)
+    spec = W.disc_tree(2, 2, 4)
+    o = oracle.OracleTree(spec)
+    t = _tree(spec)
+    x, v = _synthetic(n, 2, rng, kind)
+    ids = np.arange(n, dtype=np.int64)
+    st = pic.Stepper(t, scheme, x, v, ids=ids, device=dev)
+    st.initial_sort()
+    nb0 = o.bin_of(x, scheme) if n else np.zeros(0, np.int32)
+    perm, start = oracle.rebin(nb0, o.n_bins(scheme), None)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.ids.cpu().numpy(), perm)
+    assert np.array_equal(st.start.cpu().numpy(), start)
+    E = W.random_field(rng, 2, o.n_vertices, 0.3)
+    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    xs, vs = x[:, perm], v[:, perm]
+    st.step(Ed, -0.7, 0.7, q_uniform=-1.0)
+    x1, v1, _, nb = o.gather_push(xs, vs, E, -0.7, 0.7, scheme)
+    perm2, start2 = oracle.rebin(nb, o.n_bins(scheme), start)
+    rho = o.deposit(x1[:, perm2], None, -1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.start.cpu().numpy(), start2)
+    assert np.array_equal(st.x.cpu().numpy(), x1[:, perm2])
+    assert np.array_equal(st.v.cpu().numpy(), v1[:, perm2])
+    _check_rho(st.rho.cpu().numpy(), rho)
+    assert t.status_sync() == 0
+
+
+def test_nonfinite_and_out_of_box_are_flagged_not_fatal():
+    dev = _dev()
+    spec = W.regular_tree(2, 3)
+    t = _tree(spec)
+    rng = np.random.default_rng(3)
+    x = rng.random((2, 1000))
+    v = np.zeros((2, 1000))
+    v[0, 10] = np.nan
+    st = pic.Stepper(t, 0, x, v, device=dev)
+    st.initial_sort()
+    E = torch.zeros((2, t.n_vertices), dtype=torch.float64, device=dev)
+    st.step(E, -0.1, 0.1, q_uniform=-1.0)
+    torch.cuda.synchronize()
+    assert t.status_sync() == pic._capi.PIC_E_NONFINITE
+    assert t.status_sync() == 0                       # cleared
+    xb = torch.tensor(np.array([[0.5, 1.5], [0.5, 0.5]]), device=dev)
+    b = torch.empty(2, dtype=torch.int32, device=dev)
+    pic.locate(t, 0, xb, b)
+    assert t.status_sync() == pic._capi.PIC_E_RANGE
+    assert int(b.max()) < t.n_leaves
+
+
+def test_forest_locate_and_step_match_oracle_per_instance():
+    dev = _dev()
+    insts = W.config5(n_inst=5, n_min=2e3, n_max=3e4)
+    specs = [w.tree for w in insts]
+    t = _tree(specs)
+    counts = [w.n for w in insts]
+    inst_start = torch.tensor(np.concatenate([[0], np.cumsum(counts)]), dtype=torch.int64, device=dev)
+    x = np.concatenate([w.x for w in insts], axis=1)
+    v = np.concatenate([w.v for w in insts], axis=1)
+    for scheme in (0, 1):
+        st = pic.Stepper(t, scheme, x, v, ids=np.arange(x.shape[1]), inst_start=inst_start, device=dev)
+        st.initial_sort()
+        rng = np.random.default_rng(5)
+        Es, qmdt, dts = [], [], []
+        for i, w in enumerate(insts):
+            o = oracle.OracleTree(w.tree)
+            Es.append(W.random_field(rng, 2, o.n_vertices, 2.0 * w.h / w.dt ** 2))
+            qmdt.append(w.qm * w.dt)
+            dts.append(w.dt)
+        E = torch.tensor(np.concatenate(Es, axis=1), dtype=torch.float64, device=dev)
+        qd = torch.tensor(qmdt, dtype=torch.float64, device=dev)
+        dd = torch.tensor(dts, dtype=torch.float64, device=dev)
+        xs0 = st.x.cpu().numpy().copy()
+        vs0 = st.v.cpu().numpy().copy()
+        st.gather_push(E, 0.0, 0.0, qmdt_dev=qd, dt_dev=dd)
+        torch.cuda.synchronize()
+        xg, vg, bg = st.x.cpu().numpy(), st.v.cpu().numpy(), st.bin.cpu().numpy()
+        p0 = 0
+        for i, w in enumerate(insts):
+            o = oracle.OracleTree(w.tree)
+            ii = t.instance(i)
+            sl = slice(p0, p0 + w.n)
+            x1, v1, _, nb = o.gather_push(xs0[:, sl], vs0[:, sl], Es[i], qmdt[i], dts[i], scheme)
+            assert np.array_equal(xg[:, sl], x1) and np.array_equal(vg[:, sl], v1)
+            off = ii.leaf_offset if scheme == 0 else ii.pidt_offset
+            assert np.array_equal(bg[sl], nb + off)
+            p0 += w.n
+        st.rebin()
+        st.deposit(-1.0)
+        torch.cuda.synchronize()
+        # instance by instance the forest result equals the single-tree oracle
+        xs, starts = st.x.cpu().numpy(), st.start.cpu().numpy()
+        rho = st.rho.cpu().numpy()
+        p0 = 0
+        for i, w in enumerate(insts):
+            o = oracle.OracleTree(w.tree)
+            ii = t.instance(i)
+            off = ii.leaf_offset if scheme == 0 else ii.pidt_offset
+            nbi = o.n_bins(scheme)
+            assert np.array_equal(starts[off:off + nbi + 1] - p0, oracle.rebin(
+                o.bin_of(xs[:, p0:p0 + w.n], scheme), nbi, None)[1])
+            _check_rho(rho[ii.vertex_offset:ii.vertex_offset + ii.n_vertices],
+                       o.deposit(xs[:, p0:p0 + w.n], None, -1.0))
+            p0 += w.n
+        assert t.status_sync() == 0

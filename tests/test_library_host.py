@@ -1,0 +1,138 @@
+"""CPU checks of libpic.so: it loads, exports the C ABI, builds the same tree
+tables as the oracle (host code only, no GPU needed) and rejects bad
+arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+import paper_1508_02435_amd as pic
+from paper_1508_02435_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+TREES = [W.regular_tree(2, 3), W.regular_tree(3, 2), W.disc_tree(2, 2, 4), W.disc_tree(3, 1, 3),
+         W.disc_tree(2, 1, 3, radius=(1, 3)), W.regular_tree(2, 0), W.disc_tree(2, 4, 6)]
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "pic.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(pic_\w+)\s*\(", header, re.M))
+    assert declared == set(_capi.EXPORTS)
+    L = C.CDLL(_capi.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("spec", TREES, ids=lambda s: f"d{s.dim}L{s.max_level}")
+def test_tree_tables_equal_oracle(spec):
+    o = oracle.OracleTree(spec)
+    t = pic.Tree(spec)
+    assert (t.n_leaves, t.n_vertices, t.n_pidt) == (o.n_leaves, o.n_vertices, o.n_pidt)
+    a, b = t.leaf_table(), o.leaves()
+    for k in ("key", "level", "coord", "vtx", "pidt"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(t.vertex_table(), o.vertex_positions())
+    pa, pb = t.pidt_table(), o.pidt_bins()
+    for k in ("key", "level", "b"):
+        assert np.array_equal(pa[k], pb[k]), k
+    assert t.regular == all(lv == spec.max_level for lv in b["level"])
+
+
+def test_forest_tables_concatenate_instances():
+    specs = [W.regular_tree(2, 3), W.disc_tree(2, 2, 4), W.regular_tree(2, 2)]
+    t = pic.Tree(specs)
+    assert t.n_inst == 3 and not t.regular
+    lt = t.leaf_table()
+    off = 0
+    voff = 0
+    poff = 0
+    for i, s in enumerate(specs):
+        o = oracle.OracleTree(s)
+        ii = t.instance(i)
+        assert (ii.leaf_offset, ii.vertex_offset, ii.pidt_offset) == (off, voff, poff)
+        ol = o.leaves()
+        assert np.array_equal(lt["key"][off:off + o.n_leaves], ol["key"])
+        assert np.array_equal(lt["vtx"][off:off + o.n_leaves], ol["vtx"] + voff)
+        assert np.array_equal(lt["pidt"][off:off + o.n_leaves], ol["pidt"] + poff)
+        off += o.n_leaves
+        voff += o.n_vertices
+        poff += o.n_pidt
+    assert (t.n_leaves, t.n_vertices, t.n_pidt) == (off, voff, poff)
+
+
+def test_division_magic_is_exact():
+    """floor(n M / 2^k) == floor(n / 3^e) for n < 2^30 (Granlund-Montgomery bound)."""
+    for e in range(0, 20):
+        d = 3 ** e
+        k = 30 + (d - 1).bit_length()
+        M = (2 ** k + d - 1) // d
+        assert 2 ** k <= M * d <= 2 ** k + 2 ** (k - 30)
+        assert M * (2 ** 30) < 2 ** 64
+        for n in [0, 1, d - 1, d, d + 1, 2 ** 30 - 1, (2 ** 30 // d) * d, (2 ** 30 // d) * d - 1]:
+            if 0 <= n < 2 ** 30:
+                assert (n * M) >> k == n // d
+
+
+def _tree_handle(spec):
+    return pic.Tree(spec)
+
+
+def test_bad_tree_arguments_are_rejected():
+    L = _capi.lib()
+    h = C.c_void_p()
+    lv = (C.c_int32 * 1)(3)
+    assert L.pic_tree_create(4, 1, lv, None, C.byref(h)) == _capi.PIC_E_ARG
+    assert L.pic_tree_create(2, 0, lv, None, C.byref(h)) == _capi.PIC_E_ARG
+    assert L.pic_tree_create(2, 1, lv, None, C.byref(h)) == _capi.PIC_E_ARG     # masks missing
+    lv19 = (C.c_int32 * 1)(19)
+    assert L.pic_tree_create(2, 1, lv19, None, C.byref(h)) == _capi.PIC_E_ARG
+    lv13 = (C.c_int32 * 1)(13)
+    assert L.pic_tree_create(3, 1, lv13, None, C.byref(h)) == _capi.PIC_E_ARG   # 3^(3*13)*64 > 2^64
+    assert L.pic_tree_create(2, 1, lv, None, None) == _capi.PIC_E_ARG
+
+
+def test_calls_check_arguments_before_the_device():
+    t = pic.Tree(W.regular_tree(2, 2))
+    L = _capi.lib()
+    P = _capi.Particles()
+    P.n = 10
+    # no coordinate pointers
+    assert L.pic_gather_push(t.handle, 0, 0, C.byref(P), None, 0.0, 0.0, None, None, None, None, None) \
+        == _capi.PIC_E_ARG
+    assert L.pic_locate(t.handle, 5, 0, C.byref(P), None, None, None) == _capi.PIC_E_ARG
+    # positions alone are enough for locate and deposit (no velocities needed)
+    P.x[0], P.x[1] = 0x1000, 0x2000
+    assert L.pic_locate(t.handle, 0, 0, C.byref(P), None, C.c_void_p(0x3000), None) == _capi.PIC_E_STATE
+    # ... but gather_push needs velocities
+    E = (C.c_void_p * 3)(0x4000, 0x5000, None)
+    assert L.pic_gather_push(t.handle, 0, 0, C.byref(P), E, 0.0, 0.0, None, None, C.c_void_p(0x3000), None,
+                             None) == _capi.PIC_E_ARG
+    P.v[0], P.v[1] = 0x6000, 0x7000
+    assert L.pic_gather_push(t.handle, 0, 0, C.byref(P), E, 0.0, 0.0, None, None, C.c_void_p(0x3000), None,
+                             None) == _capi.PIC_E_STATE
+    P.n = 0
+    # nothing uploaded yet: valid arguments report the state error
+    assert L.pic_locate(t.handle, 0, 0, C.byref(P), None, None, None) == _capi.PIC_E_STATE
+    # undersized scratch is reported
+    need = pic.scratch_bytes(t, 1000, pic.PIT)
+    assert need > 0
+    fake = C.c_void_p(0x1000)
+    start = C.c_void_p(0x2000)
+    nb = C.c_void_p(0x3000)
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 0, None, None, None, start, fake, need - 1, None) \
+        == _capi.PIC_E_SCRATCH
+    # bad column width
+    cols = (C.c_void_p * 1)(0x4000)
+    outs = (C.c_void_p * 1)(0x5000)
+    w = (C.c_int32 * 1)(2)
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, outs, w, start, fake, need, None) == _capi.PIC_E_ARG
+    # aliasing columns
+    w8 = (C.c_int32 * 1)(8)
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, cols, w8, start, fake, need, None) == _capi.PIC_E_ARG
+    assert L.pic_status_sync(t.handle, None) == _capi.PIC_E_STATE
+    assert _capi.status_string(_capi.PIC_E_SCRATCH) == "scratch buffer too small"

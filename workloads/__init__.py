@@ -200,7 +200,7 @@ def langmuir_field(pos: np.ndarray, eps: float, modes: Sequence[int]) -> np.ndar
     E0 = -sum eps/(2 pi k) sin(2 pi k x0); other components vanish.
     ``pos`` has shape (dim, nv) in domain units.
     """
-    e = np.zeros_like(pos, dtype=float)
+    e = np.zeros(pos.shape)
     for k in modes:
         e[0] -= eps / (2.0 * np.pi * k) * np.sin(2.0 * np.pi * k * pos[0])
     return e
@@ -208,7 +208,7 @@ def langmuir_field(pos: np.ndarray, eps: float, modes: Sequence[int]) -> np.ndar
 
 def cosine_potential_field(pos: np.ndarray, phi0: float) -> np.ndarray:
     """E = -grad V for V = phi0 * sum_k cos(2 pi x_k)."""
-    return 2.0 * np.pi * phi0 * np.sin(2.0 * np.pi * pos)
+    return np.ascontiguousarray(2.0 * np.pi * phi0 * np.sin(2.0 * np.pi * pos))
 
 
 # ---------------------------------------------------------------------------
