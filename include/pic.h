@@ -250,6 +250,30 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
                        const double *q_dev, double q_uniform, double *rho_dev,
                        void *scratch_dev, size_t scratch_bytes, void *stream);
 
+/*
+ * One whole step in a single call: the same result as pic_gather_push, then
+ * pic_rebin (in -> out) and pic_deposit (on out), with fused kernels (paper
+ * Sec. 2 items 1, 3, 4; Sec. 4 re-binning).  The first kernel pushes a tile
+ * of particles, sorts it by new bin in LDS and writes it back in place in
+ * tile-sorted order, so the new bins never go through memory; the second
+ * moves each run of equal bin to its destination.
+ *   in                 sorted set with offsets bin_start_dev; its x, v and
+ *                      extra columns are used as workspace and hold no
+ *                      meaningful data afterwards.
+ *   extra_in/out       n_extra further columns (4 or 8 bytes) carried along.
+ *   q_column           index of the per-particle charge among the extra
+ *                      columns (8-byte), or -1 to use q_uniform.
+ *   out                receives the re-binned set; new_bin_start_dev its
+ *                      offsets; rho_dev the vertex charge.
+ * Scratch: pic_scratch_bytes().  E_p is not produced.
+ */
+pic_status pic_step(const pic_tree *tree, int32_t scheme, int32_t precision, pic_particles *in,
+                    const int64_t *bin_start_dev, const double *const *E_dev, double qmdt, double dt,
+                    const pic_push_params *params, int32_t n_extra, void *const *extra_in_dev,
+                    void *const *extra_out_dev, const int32_t *extra_bytes, int32_t q_column, double q_uniform,
+                    pic_particles *out, int64_t *new_bin_start_dev, double *rho_dev, void *scratch_dev,
+                    size_t scratch_bytes, void *stream);
+
 /* ------------------------------------------------------- measurement aids */
 
 /*
@@ -277,6 +301,22 @@ typedef struct {
 } pic_kernel_time;
 
 pic_status pic_profile_enable(int32_t on);
+
+/*
+ * Launch-shape knobs, for the autotuner.  Names and values:
+ *   "rebin_tile"    particles per rebin tile, 2048 or 4096 (default 2048);
+ *   "rebin_radix"   bits per LDS radix pass of the tile sort, 4 or 5 (default 4);
+ *   "scatter_mode"  0 = records staged through LDS, 1 = gathered straight from
+ *                   the tile (default 0);
+ *   "scatter_nt"    1 = non-temporal stores for the re-binned records (default 0);
+ *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
+ *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64).
+ * Every setting gives the same results; pic_scratch_bytes covers all of them.
+ * Affects calls enqueued afterwards.  Unknown names or values: PIC_E_ARG
+ * (pic_tune_get returns -1).
+ */
+pic_status pic_tune_set(const char *name, int64_t value);
+int64_t pic_tune_get(const char *name);
 int32_t pic_profile_read(pic_kernel_time *out, int32_t max_entries);
 
 #ifdef __cplusplus

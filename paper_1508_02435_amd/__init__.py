@@ -19,7 +19,7 @@ from . import _capi
 from ._capi import F32_OFFSET, F64, PIDT, PIT, PicError, check, lib
 
 __all__ = ["Tree", "PIT", "PIDT", "F64", "F32_OFFSET", "PicError", "locate", "gather_push", "rebin",
-           "deposit", "scratch_bytes", "Stepper", "lib"]
+           "deposit", "scratch_bytes", "Stepper", "lib", "tune", "tuning", "TUNING_KNOBS", "step"]
 
 
 def _ptr(t) -> Optional[int]:
@@ -69,6 +69,7 @@ class Tree:
         check(lib().pic_tree_create(dim, len(specs), levels.ctypes.data_as(C.c_void_p),
                                     self._masks.ctypes.data_as(C.c_void_p), C.byref(h)), "pic_tree_create")
         self._h = h
+        self._lib = lib()
         info = _capi.TreeInfo()
         check(lib().pic_tree_get_info(self._h, C.byref(info)), "pic_tree_get_info")
         self.info = info
@@ -82,8 +83,9 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().pic_tree_destroy(h)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.pic_tree_destroy(h)
             self._h = None
 
     @property
@@ -154,6 +156,19 @@ def _particles(n, x=None, v=None, off=None, u=None, inst_start=None) -> _capi.Pa
 def _check_inst(tree, inst_start):
     if tree.n_inst > 1:
         _check_vec(inst_start, tree.n_inst + 1, "inst_start")
+
+
+TUNING_KNOBS = {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1), "scatter_nt": (0, 1),
+                "scatter_group": (1, 2, 4), "deposit_lanes": (16, 32, 64)}
+
+
+def tune(name: str, value: int):
+    """Set a launch-shape knob (results do not depend on it)."""
+    check(lib().pic_tune_set(name.encode(), int(value)), f"pic_tune_set({name}={value})")
+
+
+def tuning() -> dict:
+    return {k: int(lib().pic_tune_get(k.encode())) for k in TUNING_KNOBS}
 
 
 def scratch_bytes(tree: Tree, n: int, scheme: int, precision: int = F64) -> int:
@@ -236,6 +251,41 @@ def deposit(tree: Tree, scheme: int, x, bin_start, rho, scratch, q=None, q_unifo
           "pic_deposit")
 
 
+def step(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_start, x_out, v_out, new_start, rho,
+         scratch, extra_in=(), extra_out=(), q_column: int = -1, q_uniform: float = 0.0, inst_start=None,
+         qmdt_dev=None, dt_dev=None, stream=None):
+    """Fused whole step (gather+push, re-bin into x_out/v_out, deposit); x, v are consumed."""
+    n = x.shape[1]
+    for a, nm in ((x, "x"), (v, "v"), (x_out, "x_out"), (v_out, "v_out")):
+        _check_soa(a, tree.dim, n, "float64", nm)
+    for k in range(tree.dim):
+        _check_vec(E[k], tree.n_vertices, f"E[{k}]")
+    nb = tree.n_bins(scheme)
+    _check_vec(bin_start, nb + 1, "bin_start")
+    _check_vec(new_start, nb + 1, "new_start")
+    _check_vec(rho, tree.n_vertices, "rho")
+    _check_inst(tree, inst_start)
+    _need(len(extra_in) == len(extra_out), "extra column lists differ in length")
+    for a, b in zip(extra_in, extra_out):
+        _check_vec(a, n, "extra in")
+        _check_vec(b, n, "extra out")
+    for a in (qmdt_dev, dt_dev):
+        if a is not None:
+            _check_vec(a, tree.n_inst, "per-instance parameter")
+    P = _particles(n, x=x, v=v, inst_start=inst_start)
+    Q = _particles(n, x=x_out, v=v_out, inst_start=inst_start)
+    Eptr = (C.c_void_p * 3)(*[_ptr(E[k]) if k < tree.dim else None for k in range(3)])
+    pp = _capi.PushParams(_ptr(qmdt_dev), _ptr(dt_dev))
+    ne = len(extra_in)
+    ins = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_in])
+    outs = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_out])
+    sizes = (C.c_int32 * max(ne, 1))(*[c.element_size() for c in extra_in])
+    check(lib().pic_step(tree.handle, scheme, F64, C.byref(P), C.c_void_p(_ptr(bin_start)), Eptr, float(qmdt),
+                         float(dt), C.byref(pp), ne, ins, outs, sizes, int(q_column), float(q_uniform), C.byref(Q),
+                         C.c_void_p(_ptr(new_start)), C.c_void_p(_ptr(rho)), C.c_void_p(_ptr(scratch)),
+                         scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))), "pic_step")
+
+
 class Stepper:
     """Device state of one particle set and the three calls of a time step.
 
@@ -306,6 +356,21 @@ class Stepper:
                 q_uniform=q_uniform, inst_start=self.inst_start)
 
     def step(self, E, qmdt, dt, q_uniform=0.0, **kw):
+        """Three separate calls: gather_push, rebin, deposit."""
         self.gather_push(E, qmdt, dt, **kw)
         self.rebin()
         self.deposit(q_uniform)
+
+    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+        """The same step through the single fused call."""
+        extra_in, extra_out = [], []
+        q_col = -1
+        if self.q is not None:
+            q_col = len(extra_in)
+            extra_in.append(self.q); extra_out.append(self.q2)
+        if self.ids is not None:
+            extra_in.append(self.ids); extra_out.append(self.ids2)
+        step(self.tree, self.scheme, self.x, self.v, E, qmdt, dt, self.start, self.x2, self.v2, self.start2,
+             self.rho, self.scratch, extra_in, extra_out, q_col, q_uniform, inst_start=self.inst_start,
+             qmdt_dev=qmdt_dev, dt_dev=dt_dev)
+        self._swap()

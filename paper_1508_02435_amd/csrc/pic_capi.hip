@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "pic_host.h"
 
@@ -412,6 +413,77 @@ pic_status pic_deposit(const pic_tree *t, int32_t scheme, int32_t precision, con
     if (!t->dev) return PIC_E_STATE;
     return launch_deposit(t, scheme, p, bin_start, q, q_uniform, rho, scratch, scratch_bytes,
                           (hipStream_t)stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_particles *in,
+                    const int64_t *bin_start, const double *const *E, double qmdt, double dt,
+                    const pic_push_params *params, int32_t n_extra, void *const *extra_in, void *const *extra_out,
+                    const int32_t *extra_bytes, int32_t q_column, double q_uniform, pic_particles *out,
+                    int64_t *new_bin_start, double *rho, void *scratch, size_t scratch_bytes, void *stream) {
+    if (!t || !valid_scheme(scheme) || precision != PIC_F64 || !particles_ok(t, in, precision, true) || !out)
+        return PIC_E_ARG;
+    if (out->n != in->n || !particles_ok(t, out, precision, true)) return PIC_E_ARG;
+    if (in->n > 0 && (!E || !bin_start)) return PIC_E_ARG;
+    if (in->n > 0)
+        for (int k = 0; k < t->dim; ++k)
+            if (!E[k] || in->x[k] == out->x[k] || in->v[k] == out->v[k]) return PIC_E_ARG;
+    if (!new_bin_start || !rho || !scratch) return PIC_E_ARG;
+    if (n_extra < 0 || n_extra > 16 - 2 * t->dim) return PIC_E_ARG;
+    if (n_extra > 0 && (!extra_in || !extra_out || !extra_bytes)) return PIC_E_ARG;
+    if (q_column < -1 || q_column >= n_extra) return PIC_E_ARG;
+    Cols ex{};
+    ex.n = n_extra;
+    for (int i = 0; i < n_extra; ++i) {
+        if (extra_bytes[i] != 4 && extra_bytes[i] != 8) return PIC_E_ARG;
+        if (in->n > 0 && (!extra_in[i] || !extra_out[i] || extra_in[i] == extra_out[i])) return PIC_E_ARG;
+        ex.in[i] = extra_in[i];
+        ex.out[i] = extra_out[i];
+        ex.bytes[i] = extra_bytes[i];
+    }
+    if (q_column >= 0 && extra_bytes[q_column] != 8) return PIC_E_ARG;
+    if (scratch_bytes < pic_scratch_bytes(t, in->n, scheme, precision)) return PIC_E_SCRATCH;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_step(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start, q_column, q_uniform,
+                       rho, scratch, scratch_bytes, (hipStream_t)stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+pic_status pic_tune_set(const char *name, int64_t value) {
+    if (!name) return PIC_E_ARG;
+    std::string k(name);
+    if (k == "rebin_tile") {
+        if (value != 2048 && value != 4096) return PIC_E_ARG;
+        g_tune.rebin_ipt = (int)(value / 256);
+    } else if (k == "rebin_radix") {
+        if (value != 4 && value != 5) return PIC_E_ARG;
+        g_tune.rebin_radix = (int)value;
+    } else if (k == "scatter_mode") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.scatter_mode = (int)value;
+    } else if (k == "scatter_group") {
+        if (value != 1 && value != 2 && value != 4) return PIC_E_ARG;
+        g_tune.scatter_group = (int)value;
+    } else if (k == "deposit_lanes") {
+        if (value != 16 && value != 32 && value != 64) return PIC_E_ARG;
+        g_tune.deposit_lanes = (int)value;
+    } else if (k == "scatter_nt") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.scatter_nt = (int)value;
+    } else {
+        return PIC_E_ARG;
+    }
+    return PIC_OK;
+}
+
+int64_t pic_tune_get(const char *name) {
+    if (!name) return -1;
+    std::string k(name);
+    if (k == "rebin_tile") return 256 * (int64_t)g_tune.rebin_ipt;
+    if (k == "rebin_radix") return g_tune.rebin_radix;
+    if (k == "scatter_mode") return g_tune.scatter_mode;
+    if (k == "scatter_nt") return g_tune.scatter_nt;
+    if (k == "scatter_group") return g_tune.scatter_group;
+    if (k == "deposit_lanes") return g_tune.deposit_lanes;
+    return -1;
 }
 
 pic_status pic_stream_push(int32_t dim, int64_t n, double *const *x, double *const *v, double dt, void *stream) {

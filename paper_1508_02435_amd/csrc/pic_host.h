@@ -92,11 +92,26 @@ hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t
                         const int64_t *old_start, const Cols &cols, int64_t *new_start,
                         void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme);
+
+// Launch-shape knobs (set through pic_tune_set; read at launch time).
+struct Tuning {
+    int rebin_ipt = 8;      // particles per thread in a rebin tile: 8 (2048 tile) or 16 (4096 tile)
+    int rebin_radix = 4;    // bits per LDS radix pass: 4 or 5
+    int scatter_mode = 0;   // 0: LDS-staged scatter, 1: direct gather from the tile
+    int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
+    int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
+    int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
+};
+extern Tuning g_tune;
 hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
                           const int64_t *bin_start, const double *q, double q_uniform, double *rho,
                           void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t deposit_scratch_bytes(const pic_tree *t, int scheme);
 hipError_t launch_status_clear(const pic_tree *t, hipStream_t s);
+hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
+                       const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,
+                       pic_particles *out, int64_t *new_start, int q_col, double q_uniform, double *rho,
+                       void *scratch, size_t scratch_bytes, hipStream_t s);
 hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *const *v, double dt, hipStream_t s);
 
 }  // namespace pic

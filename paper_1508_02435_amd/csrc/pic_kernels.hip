@@ -165,6 +165,83 @@ struct F64Ptrs {
 //   w_c = prod_k (bit k of c ? f_k : g_k)  multiplied in axis order,
 //   E_j = w_0 E_j[v_0] + w_1 E_j[v_1] + ...  in corner order,
 //   v_j = v_j + qmdt E_j,  x_j = x_j + v_j dt,  x_j = x_j - floor(x_j), 1 -> 0.
+// push_one updates xv, vv in place, stores E_p when P.Ep[0] is set, and
+// returns the particle's new bin; non-finite or out-of-box input sets bits
+// in `bad`.
+template <int D, int SCHEME, bool REG>
+__device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in, const F64Ptrs &P,
+                                             const int32_t *lds, int lds_n, double (&xv)[D], double (&vv)[D],
+                                             double qmdt, double dt, int64_t p, uint32_t &bad) {
+    Axis ax[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
+        if (!(vv[k] - vv[k] == 0.0)) bad |= PIC_DEV_NONFINITE;
+    }
+    // leaf holding x: coordinates a, width s, corner vertex ids
+    uint32_t I[D], a[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) I[k] = ax[k].T >> 1;
+    int lev = in.L;
+    int32_t vid[1 << D];
+    if (REG) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) a[k] = I[k];
+        const uint32_t S = (uint32_t)in.S;
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) {
+            uint32_t idx = 0, m = 1;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                uint32_t j = I[k] + ((c >> k) & 1);
+                if (j >= S) j -= S;
+                idx += j * m;
+                m *= S;
+            }
+            vid[c] = in.vtx_off + (int32_t)idx;
+        }
+    } else {
+        const uint32_t rank = descend<D>(t, in, I, lds, lds_n, lev);
+#pragma unroll
+        for (int k = 0; k < D; ++k) a[k] = div_pow3(I[k], in.L - lev);
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) vid[c] = t.leaf_vtx[(int64_t)rank * (1 << D) + c];
+    }
+    const double s = (double)pow3_u32(in.L - lev);
+    const double rinv = in.rinv[lev];
+    double f[D], g[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
+        g[k] = __dsub_rn(1.0, f[k]);
+    }
+    double w[1 << D];
+#pragma unroll
+    for (int c = 0; c < (1 << D); ++c) {
+        double wc = (c & 1) ? f[0] : g[0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
+        w[c] = wc;
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double *Ej = P.E[j];
+        double e = __dmul_rn(w[0], Ej[vid[0]]);
+#pragma unroll
+        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ej[vid[c]]));
+        if (P.Ep[0]) P.Ep[j][p] = e;
+        double vj = __dadd_rn(vv[j], __dmul_rn(qmdt, e));
+        double xj = __dadd_rn(xv[j], __dmul_rn(vj, dt));
+        xj = __dsub_rn(xj, floor(xj));
+        if (xj == 1.0) xj = 0.0;
+        vv[j] = vj;
+        xv[j] = xj;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
+    return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
+}
+
 template <int D, int SCHEME, bool REG, bool MULTI>
 __global__ __launch_bounds__(256) void k_gather_push(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
                                                      double qmdt0, double dt0, const double *qmdt_arr,
@@ -186,81 +263,13 @@ __global__ __launch_bounds__(256) void k_gather_push(DevTree t, DevInst in0, F64
             xv[k] = P.x[k][p];
             vv[k] = P.v[k][p];
         }
-        Axis ax[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
-            if (!(vv[k] - vv[k] == 0.0)) bad |= PIC_DEV_NONFINITE;
-        }
-        // leaf holding x: coordinates a, width s, corner vertex ids
-        uint32_t I[D], a[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) I[k] = ax[k].T >> 1;
-        int lev = in.L;
-        int32_t vid[1 << D];
-        if (REG) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) a[k] = I[k];
-            const uint32_t S = (uint32_t)in.S;
-#pragma unroll
-            for (int c = 0; c < (1 << D); ++c) {
-                uint32_t idx = 0, m = 1;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    uint32_t j = I[k] + ((c >> k) & 1);
-                    if (j >= S) j -= S;
-                    idx += j * m;
-                    m *= S;
-                }
-                vid[c] = in.vtx_off + (int32_t)idx;
-            }
-        } else {
-            const uint32_t rank = descend<D>(t, in, I, lds, lds_n, lev);
-#pragma unroll
-            for (int k = 0; k < D; ++k) a[k] = div_pow3(I[k], in.L - lev);
-#pragma unroll
-            for (int c = 0; c < (1 << D); ++c) vid[c] = t.leaf_vtx[(int64_t)rank * (1 << D) + c];
-        }
-        const double s = (double)pow3_u32(in.L - lev);
-        const double rinv = in.rinv[lev];
-        double f[D], g[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
-            g[k] = __dsub_rn(1.0, f[k]);
-        }
-        double w[1 << D];
-#pragma unroll
-        for (int c = 0; c < (1 << D); ++c) {
-            double wc = (c & 1) ? f[0] : g[0];
-#pragma unroll
-            for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
-            w[c] = wc;
-        }
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const double *Ej = P.E[j];
-            double e = __dmul_rn(w[0], Ej[vid[0]]);
-#pragma unroll
-            for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ej[vid[c]]));
-            if (P.Ep[0]) P.Ep[j][p] = e;
-            double vj = __dadd_rn(vv[j], __dmul_rn(qmdt, e));
-            double xj = __dadd_rn(xv[j], __dmul_rn(vj, dt));
-            xj = __dsub_rn(xj, floor(xj));
-            if (xj == 1.0) xj = 0.0;
-            vv[j] = vj;
-            xv[j] = xj;
-        }
+        const uint32_t nb = push_one<D, SCHEME, REG>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             P.x[k][p] = xv[k];
             P.v[k][p] = vv[k];
         }
-        uint32_t dummy = 0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, dummy);
-        bad |= dummy;
-        bin_out[p] = bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
+        bin_out[p] = nb;
         if (bad) flag_status(t.status, bad);
     }
 }
@@ -312,10 +321,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
 // ------------------------------------------------------------------- rebin
 
 constexpr int RB_THREADS = 256;
-constexpr int RB_IPT = 16;
-constexpr int RB_TILE = RB_THREADS * RB_IPT;   // 4096 particles per tile
-constexpr int RB_RADIX = 4;                    // bits per LDS radix pass
-constexpr int RB_DIGITS = 1 << RB_RADIX;
+constexpr int RB_MAX_TILE = 4096;
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -323,6 +329,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 struct RebinScratch {
+    uint32_t *tile_bin;   // n_tiles * 2: bin holding the first slot, 1 + bin holding the last slot
     uint16_t *perm;       // n_tiles * TILE: tile-local source index per sorted slot
     uint32_t *run_key;    // n_tiles * TILE
     uint32_t *run_info;   // start | count << 16
@@ -338,78 +345,92 @@ struct RebinScratch {
     uint32_t *scan_ctr;   // dynamic block counter (zeroed per call)
 };
 
-// Pass 1: per tile, stable LDS radix sort of particle slots by key
-// 2*bin + arrived, emitting runs of equal key.
-__global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_bin, const int64_t *old_start,
-                                                           int64_t n, uint32_t n_bins, RebinScratch sc,
-                                                           uint32_t *status) {
-    __shared__ uint32_t s_key[RB_TILE];
-    __shared__ uint16_t s_item[2][RB_TILE];
-    __shared__ uint32_t s_cnt[RB_DIGITS * RB_THREADS + 1];   // +1: run-start sentinel
-    __shared__ uint32_t s_wsum[4];
-    __shared__ uint32_t s_misc[4];
+// Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
+// padded by one word every 32 so that both the per-thread column accesses of
+// the counting phase and the per-thread row segments of the scan phase fall
+// into distinct banks.
+__device__ __forceinline__ int cpad(int f) { return f + (f >> 5); }
+
+// Pass 1: per tile, a stable LDS radix sort of the particle slots groups them
+// into runs of equal key 2*bin + arrived.  IPT slots per thread, RADIX bits
+// per pass.  Each thread counts the digits of its own slots in registers
+// (8-bit counters packed in 64-bit words), so a pass costs a few independent
+// LDS round trips instead of a read-modify-write chain per slot.
+template <int IPT, int RADIX, bool STAGE>
+struct TileSmem {
+    static constexpr int TILE = RB_THREADS * IPT;
+    static constexpr int DIG = 1 << RADIX;
+    static constexpr int NCNT_PAD = DIG * RB_THREADS + DIG * RB_THREADS / 32 + 1;
+    // the counter area doubles as run-start table and, with STAGE, as an
+    // 8-byte staging buffer for one column of the tile
+    static constexpr int NSCR = (STAGE && 2 * TILE > NCNT_PAD) ? 2 * TILE : (NCNT_PAD > TILE + 1 ? NCNT_PAD : TILE + 1);
+    uint32_t key[TILE];
+    uint16_t item[2][TILE];
+    uint32_t cnt[NSCR];
+    uint32_t wsum[4];
+    uint32_t misc[4];
+};
+
+// On entry S.key[i] holds the new bin of tile slot i (i < cnt) and all
+// threads have passed a barrier.  Sorts the slots by (bin, arrived), writes
+// the tile's run table and key counts, and returns the item buffer that
+// holds the sorted order (sorted slot -> tile slot).  S.cnt holds the run
+// starts afterwards (n_runs + 1 entries).
+template <int IPT, int RADIX, bool STAGE>
+__device__ int tile_sort_emit(TileSmem<IPT, RADIX, STAGE> &S, const int64_t *old_start, int64_t tile, int cnt,
+                              uint32_t n_bins, RebinScratch &sc, uint32_t *status, uint32_t &n_runs_out) {
+    constexpr int TILE = RB_THREADS * IPT;
+    constexpr int DIG = 1 << RADIX;
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
-    const int64_t lo = tile * RB_TILE;
-    const int cnt = (int)min((int64_t)RB_TILE, n - lo);
+    const int64_t lo = tile * TILE;
+    uint32_t nbv[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int i = tid * IPT + j;
+        uint32_t nb = i < cnt ? S.key[i] : 0u;
+        if (i < cnt && nb >= n_bins) {
+            flag_status(status, PIC_DEV_RANGE);
+            nb = n_bins - 1;
+        }
+        nbv[j] = nb;
+    }
+    __syncthreads();
 
     // old bin of each slot: the segment of old_start that holds it
     if (old_start) {
-        for (int i = tid; i < RB_TILE; i += RB_THREADS) s_cnt[i] = 0;  // head counts (reuse)
+        for (int i = tid; i < TILE; i += RB_THREADS) S.cnt[i] = 0;  // head counts
+        // b0: the bin holding slot 0; bins in (b0, b1) start inside the tile
         if (tid == 0) {
-            // first bin b with old_start[b] <= lo < old_start[b+1]; last bin starting before lo+cnt
-            int64_t a = 0, b = n_bins;  // upper_bound of lo in old_start[0..n_bins]
-            while (a < b) {
-                int64_t m = (a + b) >> 1;
-                if (old_start[m] <= lo) a = m + 1; else b = m;
-            }
-            s_misc[0] = (uint32_t)(a - 1);
-            int64_t hi = lo + cnt - 1;
-            int64_t c = a > 0 ? a - 1 : 0, d = n_bins;   // a >= 1 unless the offsets are malformed
-            while (c < d) {
-                int64_t m = (c + d) >> 1;
-                if (old_start[m] <= hi) c = m + 1; else d = m;
-            }
-            s_misc[1] = (uint32_t)c;  // bins in (first, c) start inside the tile
+            S.misc[0] = min(sc.tile_bin[2 * tile], n_bins - 1);
+            S.misc[1] = min(sc.tile_bin[2 * tile + 1], n_bins);
         }
         __syncthreads();
-        const uint32_t b0 = s_misc[0], b1 = s_misc[1];
+        const uint32_t b0 = S.misc[0], b1 = S.misc[1];
         for (uint32_t b = b0 + 1 + tid; b < b1; b += RB_THREADS) {
             const int64_t at = old_start[b] - lo;
-            if (at >= 0 && at < cnt) atomicAdd(&s_cnt[(int)at], 1u);
+            if (at >= 0 && at < cnt) atomicAdd(&S.cnt[(int)at], 1u);
         }
         __syncthreads();
         // inclusive scan of head counts: slot i lies in bin b0 + heads(<= i)
-        uint32_t loc[RB_IPT];
+        uint32_t loc[IPT];
         uint32_t sum = 0;
 #pragma unroll
-        for (int j = 0; j < RB_IPT; ++j) {
-            sum += s_cnt[tid * RB_IPT + j];
+        for (int j = 0; j < IPT; ++j) {
+            sum += S.cnt[tid * IPT + j];
             loc[j] = sum;
         }
         uint32_t tot;
-        uint32_t base = block_excl_scan(sum, s_wsum, &tot);
+        uint32_t base = block_excl_scan(sum, S.wsum, &tot);
 #pragma unroll
-        for (int j = 0; j < RB_IPT; ++j) {
-            const int i = tid * RB_IPT + j;
-            if (i < cnt) {
-                uint32_t nb = new_bin[lo + i];
-                if (nb >= n_bins) {
-                    flag_status(status, PIC_DEV_RANGE);
-                    nb = n_bins - 1;
-                }
-                const uint32_t ob = b0 + base + loc[j];
-                s_key[i] = 2u * nb + (nb != ob ? 1u : 0u);
-            }
+        for (int j = 0; j < IPT; ++j) {
+            const int i = tid * IPT + j;
+            if (i < cnt) S.key[i] = 2u * nbv[j] + (nbv[j] != b0 + base + loc[j] ? 1u : 0u);
         }
     } else {
-        for (int i = tid; i < cnt; i += RB_THREADS) {
-            uint32_t nb = new_bin[lo + i];
-            if (nb >= n_bins) {
-                flag_status(status, PIC_DEV_RANGE);
-                nb = n_bins - 1;
-            }
-            s_key[i] = 2u * nb + 1u;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int i = tid * IPT + j;
+            if (i < cnt) S.key[i] = 2u * nbv[j] + 1u;
         }
     }
     __syncthreads();
@@ -417,30 +438,30 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_
     // key range of the tile -> number of radix passes
     uint32_t kmin = 0xffffffffu, kmax = 0;
     for (int i = tid; i < cnt; i += RB_THREADS) {
-        kmin = min(kmin, s_key[i]);
-        kmax = max(kmax, s_key[i]);
+        kmin = min(kmin, S.key[i]);
+        kmax = max(kmax, S.key[i]);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
         kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
     }
-    if (tid == 0) { s_misc[2] = 0xffffffffu; s_misc[3] = 0; }
+    if (tid == 0) { S.misc[2] = 0xffffffffu; S.misc[3] = 0; }
     __syncthreads();
     if ((tid & 63) == 0) {
-        atomicMin(&s_misc[2], kmin);
-        atomicMax(&s_misc[3], kmax);
+        atomicMin(&S.misc[2], kmin);
+        atomicMax(&S.misc[3], kmax);
     }
     __syncthreads();
-    kmin = s_misc[2];
-    kmax = s_misc[3];
+    kmin = S.misc[2];
+    kmax = S.misc[3];
     const uint32_t span = kmax - kmin;
     const int bits = span ? 32 - __clz(span) : 0;
-    const int passes = (bits + RB_RADIX - 1) / RB_RADIX;
+    const int passes = (bits + RADIX - 1) / RADIX;
 
-    for (int i = tid; i < RB_TILE; i += RB_THREADS) {
-        if (i < cnt) s_key[i] -= kmin;
-        s_item[0][i] = (uint16_t)i;
+    for (int i = tid; i < TILE; i += RB_THREADS) {
+        if (i < cnt) S.key[i] -= kmin;
+        S.item[0][i] = (uint16_t)i;
     }
     __syncthreads();
 
@@ -448,82 +469,206 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_
     // of the current order, so ranks within a digit follow slot order.
     int cur = 0;
     for (int ps = 0; ps < passes; ++ps) {
-        const int shift = ps * RB_RADIX;
+        const int shift = ps * RADIX;
+        constexpr int NW = DIG / 8;                       // 64-bit words of 8-bit counters
+        uint8_t dig[IPT], rk[IPT];
+        uint16_t it[IPT];
 #pragma unroll
-        for (int dg = 0; dg < RB_DIGITS; ++dg) s_cnt[dg * RB_THREADS + tid] = 0;
-        uint8_t dig[RB_IPT], rk[RB_IPT];
-        uint16_t it[RB_IPT];
+        for (int j = 0; j < IPT; ++j) it[j] = S.item[cur][tid * IPT + j];
 #pragma unroll
-        for (int j = 0; j < RB_IPT; ++j) {
-            const int slot = tid * RB_IPT + j;
-            it[j] = s_item[cur][slot];
-            uint32_t dgt = RB_DIGITS - 1;                  // padding slots sort last
-            if (slot < cnt) dgt = (s_key[it[j]] >> shift) & (RB_DIGITS - 1);
-            dig[j] = (uint8_t)dgt;
-            const uint32_t r = s_cnt[dgt * RB_THREADS + tid];
-            rk[j] = (uint8_t)r;
-            s_cnt[dgt * RB_THREADS + tid] = r + 1;
+        for (int j = 0; j < IPT; ++j)                      // padding slots sort last
+            dig[j] = (uint8_t)(tid * IPT + j < cnt ? (S.key[it[j]] >> shift) & (DIG - 1) : DIG - 1);
+        uint64_t cw[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) cw[q] = 0;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int w = dig[j] >> 3, sh = (dig[j] & 7) * 8;
+            uint64_t word = cw[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) word = w == q ? cw[q] : word;
+            rk[j] = (uint8_t)((word >> sh) & 0xffu);
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                if (w == q) cw[q] += 1ull << sh;
         }
+#pragma unroll
+        for (int dg = 0; dg < DIG; ++dg)
+            S.cnt[cpad(dg * RB_THREADS + tid)] = (uint32_t)((cw[dg >> 3] >> ((dg & 7) * 8)) & 0xffu);
         __syncthreads();
-        // exclusive scan over (digit, thread) in digit-major order
-        uint32_t v[RB_DIGITS];
+        // exclusive scan over (digit, thread) in digit-major order: thread t
+        // owns the flattened counters [t*DIG, (t+1)*DIG)
+        uint32_t v[DIG];
         uint32_t sum = 0;
 #pragma unroll
-        for (int j = 0; j < RB_DIGITS; ++j) {
-            v[j] = s_cnt[tid * RB_DIGITS + j];
+        for (int j = 0; j < DIG; ++j) {
+            v[j] = S.cnt[cpad(tid * DIG + j)];
             sum += v[j];
         }
         uint32_t tot;
-        uint32_t base = block_excl_scan(sum, s_wsum, &tot);
+        uint32_t base = block_excl_scan(sum, S.wsum, &tot);
 #pragma unroll
-        for (int j = 0; j < RB_DIGITS; ++j) {
-            s_cnt[tid * RB_DIGITS + j] = base;
+        for (int j = 0; j < DIG; ++j) {
+            S.cnt[cpad(tid * DIG + j)] = base;
             base += v[j];
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < RB_IPT; ++j) {
-            const uint32_t pos = s_cnt[dig[j] * RB_THREADS + tid] + rk[j];
-            s_item[cur ^ 1][pos] = it[j];
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t pos = S.cnt[cpad(dig[j] * RB_THREADS + tid)] + rk[j];
+            S.item[cur ^ 1][pos] = it[j];
         }
         __syncthreads();
         cur ^= 1;
     }
 
     // runs of equal key in sorted order
-    uint32_t head[RB_IPT];
+    uint32_t head[IPT];
     uint32_t nh = 0;
 #pragma unroll
-    for (int j = 0; j < RB_IPT; ++j) {
-        const int slot = tid * RB_IPT + j;
+    for (int j = 0; j < IPT; ++j) {
+        const int slot = tid * IPT + j;
         uint32_t h = 0;
         if (slot < cnt) {
-            const uint32_t k = s_key[s_item[cur][slot]];
-            h = (slot == 0) || (k != s_key[s_item[cur][slot - 1]]);
+            const uint32_t k = S.key[S.item[cur][slot]];
+            h = (slot == 0) || (k != S.key[S.item[cur][slot - 1]]);
         }
         head[j] = h;
         nh += h;
     }
     uint32_t n_runs;
-    uint32_t rbase = block_excl_scan(nh, s_wsum, &n_runs);
-    // run start positions into s_cnt (reused), then counts
+    uint32_t rbase = block_excl_scan(nh, S.wsum, &n_runs);
+    // run start positions into S.cnt, then counts
     uint32_t r = rbase;
 #pragma unroll
-    for (int j = 0; j < RB_IPT; ++j)
-        if (head[j]) s_cnt[r++] = (uint32_t)(tid * RB_IPT + j);
-    if (tid == 0) s_cnt[n_runs] = (uint32_t)cnt;
+    for (int j = 0; j < IPT; ++j)
+        if (head[j]) S.cnt[r++] = (uint32_t)(tid * IPT + j);
+    if (tid == 0) S.cnt[n_runs] = (uint32_t)cnt;
     __syncthreads();
-    const int64_t rt = tile * RB_TILE;
+    const int64_t rt = tile * TILE;
     for (uint32_t q = tid; q < n_runs; q += RB_THREADS) {
-        const uint32_t st = s_cnt[q], len = s_cnt[q + 1] - st;
-        const uint32_t key = s_key[s_item[cur][st]] + kmin;
+        const uint32_t st = S.cnt[q], len = S.cnt[q + 1] - st;
+        const uint32_t key = S.key[S.item[cur][st]] + kmin;
         sc.run_key[rt + q] = key;
         sc.run_info[rt + q] = st | (len << 16);
         atomicAdd(&sc.key_cnt[key], len);
         atomicAdd(&sc.key_nruns[key], 1u);
     }
-    for (int i = tid; i < cnt; i += RB_THREADS) sc.perm[rt + i] = s_item[cur][i];
     if (tid == 0) sc.tile_nruns[tile] = n_runs;
+    n_runs_out = n_runs;
+    return cur;
+}
+
+template <int IPT, int RADIX>
+__global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_bin, const int64_t *old_start,
+                                                           int64_t n, uint32_t n_bins, RebinScratch sc,
+                                                           uint32_t *status) {
+    constexpr int TILE = RB_THREADS * IPT;
+    __shared__ TileSmem<IPT, RADIX, false> S;
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t lo = tile * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int i = tid + j * RB_THREADS;
+        if (i < cnt) S.key[i] = new_bin[lo + i];
+    }
+    __syncthreads();
+    uint32_t n_runs;
+    const int cur = tile_sort_emit<IPT, RADIX, false>(S, old_start, tile, cnt, n_bins, sc, status, n_runs);
+    for (int i = tid; i < cnt; i += RB_THREADS) sc.perm[lo + i] = S.item[cur][i];
+}
+
+// Fused first pass of a whole step: gather + push of the tile's particles
+// (thread t holds slots t + 256 j), their new bins go straight into the tile
+// sort, and the pushed columns (and the extra columns) are written back in
+// place in the tile's sorted order, staged through LDS one column at a time.
+// The new bins never travel through memory, and the tile sort's LDS work
+// overlaps the memory traffic of the other blocks.
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_push_sort(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                         double qmdt0, double dt0, const double *qmdt_arr,
+                                                         const double *dt_arr, const int64_t *inst_start,
+                                                         const int64_t *old_start, uint32_t n_bins,
+                                                         RebinScratch sc, Cols extra) {
+    constexpr int TILE = RB_THREADS * IPT;
+    __shared__ TileSmem<IPT, 4, true> S;
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t lo = tile * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+    double xv[IPT][D], vv[IPT][D];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int i = tid + j * RB_THREADS;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xv[j][k] = i < cnt ? P.x[k][lo + i] : 0.0;
+            vv[j][k] = i < cnt ? P.v[k][lo + i] : 0.0;
+        }
+    }
+    uint32_t bad = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int i = tid + j * RB_THREADS;
+        if (i < cnt) {
+            const int64_t p = lo + i;
+            int ii = 0;
+            if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+            const DevInst &in = MULTI ? t.inst[ii] : in0;
+            const double qmdt = (MULTI && qmdt_arr) ? qmdt_arr[ii] : qmdt0;
+            const double dt = (MULTI && dt_arr) ? dt_arr[ii] : dt0;
+            S.key[i] = push_one<D, SCHEME, REG>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
+        }
+    }
+    if (bad) flag_status(t.status, bad);
+    __syncthreads();
+    uint32_t n_runs;
+    const int cur = tile_sort_emit<IPT, 4, true>(S, old_start, tile, cnt, n_bins, sc, t.status, n_runs);
+    // write back in sorted order: one column at a time through the staging area
+    uint64_t *stage = (uint64_t *)S.cnt;
+    uint16_t src[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) src[j] = S.item[cur][tid + j * RB_THREADS];
+    for (int c = 0; c < 2 * D + extra.n; ++c) {
+        const int ce = c - 2 * D;
+        uint64_t ev[IPT];
+        if (c >= 2 * D) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const int i = tid + j * RB_THREADS;
+                ev[j] = 0;
+                if (i < cnt)
+                    ev[j] = extra.bytes[ce] == 8 ? ((const uint64_t *)extra.in[ce])[lo + i]
+                                                 : (uint64_t)((const uint32_t *)extra.in[ce])[lo + i];
+            }
+        }
+        __syncthreads();                                  // staging area free (run starts read)
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            uint64_t w;
+            if (c < D) w = __double_as_longlong(xv[j][c]);
+            else if (c < 2 * D) w = __double_as_longlong(vv[j][c - D]);
+            else w = ev[j];
+            stage[tid + j * RB_THREADS] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int i = tid + j * RB_THREADS;
+            if (i < cnt) {
+                const uint64_t w = stage[src[j]];
+                if (c < D) P.x[c][lo + i] = __longlong_as_double(w);
+                else if (c < 2 * D) P.v[c - D][lo + i] = __longlong_as_double(w);
+                else if (extra.bytes[ce] == 8) ((uint64_t *)extra.in[ce])[lo + i] = w;
+                else ((uint32_t *)extra.in[ce])[lo + i] = (uint32_t)w;
+            }
+        }
+    }
+    (void)n_runs;
 }
 
 // Pass 2: single-pass scan (decoupled look-back) of the per-key (count, runs)
@@ -609,11 +754,11 @@ __global__ __launch_bounds__(256) void k_rebin_scan(uint32_t n_keys, uint32_t n_
 }
 
 // Pass 3a: append every run to the list of its key (slot order arbitrary).
-__global__ __launch_bounds__(256) void k_rebin_lists(RebinScratch sc) {
+__global__ __launch_bounds__(256) void k_rebin_lists(RebinScratch sc, int tile_slots) {
     const int64_t tile = blockIdx.x;
     const uint32_t nr = sc.tile_nruns[tile];
     for (uint32_t q = threadIdx.x; q < nr; q += blockDim.x) {
-        const uint32_t a = (uint32_t)(tile * RB_TILE + q);
+        const uint32_t a = (uint32_t)(tile * tile_slots + q);
         const uint32_t key = sc.run_key[a];
         const uint32_t slot = sc.list_off[key] + atomicAdd(&sc.key_fill[key], 1u);
         sc.list[slot] = a;
@@ -621,52 +766,145 @@ __global__ __launch_bounds__(256) void k_rebin_lists(RebinScratch sc) {
 }
 
 // Pass 3b: a run's place among the runs of its key is the particle count of
-// the runs of that key in earlier tiles (lower run address).
-__global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc) {
-    const int64_t tile = blockIdx.x;
-    const uint32_t nr = sc.tile_nruns[tile];
-    for (uint32_t q = threadIdx.x; q < nr; q += blockDim.x) {
-        const uint32_t a = (uint32_t)(tile * RB_TILE + q);
-        const uint32_t key = sc.run_key[a];
-        const uint32_t l0 = sc.list_off[key], l1 = sc.list_off[key + 1];
-        uint32_t before = 0;
-        for (uint32_t j = l0; j < l1; ++j) {
-            const uint32_t b = sc.list[j];
-            if (b < a) before += sc.run_info[b] >> 16;
+// the key's runs from earlier tiles (lower run address).  Each wavefront
+// takes four keys, one per 16-lane group; a list of up to 16 runs is sorted by
+// address with a bitonic sort inside its group and prefix-summed.  Longer
+// lists are then handled by the whole wavefront: up to 64 runs with a 64-lane
+// bitonic sort, beyond that by counting the smaller addresses per run.
+template <int W>
+__device__ __forceinline__ void place_sorted(RebinScratch &sc, uint32_t l0, uint32_t len, uint32_t kb, int sub) {
+    uint32_t a = 0xffffffffu, c = 0;
+    if ((uint32_t)sub < len) {
+        a = sc.list[l0 + sub];
+        c = sc.run_info[a] >> 16;
+    }
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t oa = (uint32_t)__shfl_xor((int)a, j, 64);
+            const uint32_t oc = (uint32_t)__shfl_xor((int)c, j, 64);
+            const bool up = (sub & k) == 0;
+            const bool lower = (sub & j) == 0;
+            const bool take = lower == up ? (oa < a) : (oa > a);
+            if (take) { a = oa; c = oc; }
         }
-        sc.run_dest[a] = sc.key_base[key] + before;
+    }
+    uint32_t x = c;
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o, W);
+        if (sub >= o) x += y;
+    }
+    if ((uint32_t)sub < len) sc.run_dest[a] = kb + x - c;
+}
+
+__global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc, uint32_t n_keys) {
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, sub = lane & 15;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t k0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4; k0 < n_keys;
+         k0 += waves * 4) {
+        const int64_t key = k0 + grp;
+        uint32_t l0 = 0, len = 0, kb = 0;
+        if (key < n_keys) {
+            l0 = sc.list_off[key];
+            len = sc.list_off[key + 1] - l0;
+            kb = sc.key_base[key];
+        }
+        if (len <= 16) place_sorted<16>(sc, l0, len, kb, sub);   // len 0: nothing written
+        // keys with longer lists: whole wavefront, one after the other
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t gl0 = (uint32_t)__shfl((int)l0, g * 16, 64);
+            const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
+            const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
+            if (glen <= 16) continue;
+            if (glen <= 64) {
+                place_sorted<64>(sc, gl0, glen, gkb, lane);
+            } else {
+                for (uint32_t q = lane; q < glen; q += 64) {
+                    const uint32_t a = sc.list[gl0 + q];
+                    uint32_t before = 0;
+                    for (uint32_t j = gl0; j < gl0 + glen; ++j) {
+                        const uint32_t bb = sc.list[j];
+                        if (bb < a) before += sc.run_info[bb] >> 16;
+                    }
+                    sc.run_dest[a] = gkb + before;
+                }
+            }
+        }
     }
 }
 
-// Pass 4: LDS-staged scatter.  Thread t handles sorted slots t + 256 i, so a
-// wavefront writes 64 consecutive slots, which are consecutive destinations
-// inside a run.
+// Pass 4: scatter.  Mode 0 stages each column of the tile through LDS:
+// thread t loads the slots t + 256 i in old order (coalesced), and after a
+// barrier writes the sorted slots t + 256 i, so a wavefront writes 64
+// consecutive sorted slots, i.e. consecutive destinations inside a run.  All
+// global loads of the tile (run table, permutation, up to four columns) are
+// issued before the first one is waited for, so a block pays one memory
+// latency instead of one per step.  Mode 1 does not stage: each sorted slot
+// loads its record straight from the tile (an L2-resident window).
+template <typename T, bool NT>
+__device__ __forceinline__ void put_out(T *p, T v) {
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <int IPT, int MODE, bool NT, int SC_GROUP>
 __global__ __launch_bounds__(RB_THREADS) void k_rebin_scatter(int64_t n, RebinScratch sc, Cols cols,
                                                              uint32_t *status) {
-    __shared__ uint16_t s_rstart[RB_TILE + 1];
-    __shared__ uint32_t s_rdest[RB_TILE];
-    __shared__ uint64_t s_stage[RB_TILE];
+    constexpr int TILE = RB_THREADS * IPT;
+    __shared__ uint16_t s_rstart[TILE + 1];
+    __shared__ uint32_t s_rdest[TILE];
+    __shared__ uint64_t s_stage[MODE == 0 ? TILE : 1];
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int64_t lo = tile * RB_TILE;
-    const int cnt = (int)min((int64_t)RB_TILE, n - lo);
+    const int64_t lo = tile * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+    // speculative run-table loads (the first 256 entries of the tile's area
+    // are always in range), issued together with the rest
     const uint32_t nr = sc.tile_nruns[tile];
-    for (uint32_t q = tid; q < nr; q += RB_THREADS) {
+    const uint32_t ri0 = sc.run_info[lo + tid];
+    const uint32_t rd0 = sc.run_dest[lo + tid];
+    uint16_t src[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int j = tid + i * RB_THREADS;
+        src[i] = j < cnt ? sc.perm[lo + j] : (uint16_t)0;
+    }
+    uint64_t val[SC_GROUP][IPT];
+    const int ng = min(cols.n, SC_GROUP);
+    if (MODE == 0) {
+#pragma unroll
+        for (int c = 0; c < SC_GROUP; ++c) {
+            if (c >= ng) break;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int j = tid + i * RB_THREADS;
+                val[c][i] = 0;
+                if (j < cnt)
+                    val[c][i] = cols.bytes[c] == 8 ? ((const uint64_t *)cols.in[c])[lo + j]
+                                                   : (uint64_t)((const uint32_t *)cols.in[c])[lo + j];
+            }
+        }
+    }
+    if ((uint32_t)tid < nr) {
+        s_rstart[tid] = (uint16_t)(ri0 & 0xffffu);
+        s_rdest[tid] = rd0;
+    }
+    for (uint32_t q = tid + RB_THREADS; q < nr; q += RB_THREADS) {
         s_rstart[q] = (uint16_t)(sc.run_info[lo + q] & 0xffffu);
         s_rdest[q] = sc.run_dest[lo + q];
     }
     if (tid == 0) s_rstart[nr] = (uint16_t)min(cnt, 0xffff);
     __syncthreads();
-    uint32_t dst[RB_IPT];
-    uint16_t src[RB_IPT];
+    uint32_t dst[IPT];
 #pragma unroll
-    for (int i = 0; i < RB_IPT; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         const int j = tid + i * RB_THREADS;
-        dst[i] = 0;
-        src[i] = 0;
+        dst[i] = 0xffffffffu;
         if (j < cnt) {
-            src[i] = sc.perm[lo + j];
-            // run holding slot j: last run start <= j
+            // run holding sorted slot j: last run start <= j
             uint32_t a = 0, b = nr - 1;
             while (a < b) {
                 const uint32_t m = (a + b + 1) >> 1;
@@ -679,62 +917,253 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_scatter(int64_t n, RebinSc
             }
         }
     }
-    for (int c = 0; c < cols.n; ++c) {
-        if (cols.bytes[c] == 8) {
-            const uint64_t *in = (const uint64_t *)cols.in[c] + lo;
-            uint64_t *out = (uint64_t *)cols.out[c];
+    if (MODE == 1) {
+        for (int c = 0; c < cols.n; ++c) {
+            if (cols.bytes[c] == 8) {
+                const uint64_t *in = (const uint64_t *)cols.in[c] + lo;
+                uint64_t *out = (uint64_t *)cols.out[c];
+                uint64_t v[IPT];
 #pragma unroll
-            for (int i = 0; i < RB_IPT; ++i) {
-                const int j = tid + i * RB_THREADS;
-                if (j < cnt) s_stage[j] = in[j];
-            }
-            __syncthreads();
+                for (int i = 0; i < IPT; ++i) v[i] = dst[i] != 0xffffffffu ? in[src[i]] : 0;
 #pragma unroll
-            for (int i = 0; i < RB_IPT; ++i) {
-                const int j = tid + i * RB_THREADS;
-                if (j < cnt && dst[i] != 0xffffffffu) out[dst[i]] = s_stage[src[i]];
-            }
-        } else {
-            const uint32_t *in = (const uint32_t *)cols.in[c] + lo;
-            uint32_t *out = (uint32_t *)cols.out[c];
-            uint32_t *st = (uint32_t *)s_stage;
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) put_out<uint64_t, NT>(&out[dst[i]], v[i]);
+            } else {
+                const uint32_t *in = (const uint32_t *)cols.in[c] + lo;
+                uint32_t *out = (uint32_t *)cols.out[c];
+                uint32_t v[IPT];
 #pragma unroll
-            for (int i = 0; i < RB_IPT; ++i) {
-                const int j = tid + i * RB_THREADS;
-                if (j < cnt) st[j] = in[j];
-            }
-            __syncthreads();
+                for (int i = 0; i < IPT; ++i) v[i] = dst[i] != 0xffffffffu ? in[src[i]] : 0;
 #pragma unroll
-            for (int i = 0; i < RB_IPT; ++i) {
-                const int j = tid + i * RB_THREADS;
-                if (j < cnt && dst[i] != 0xffffffffu) out[dst[i]] = st[src[i]];
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) put_out<uint32_t, NT>(&out[dst[i]], v[i]);
             }
         }
-        __syncthreads();
+        return;
+    }
+    for (int c0 = 0; c0 < cols.n; c0 += SC_GROUP) {
+        if (c0 > 0) {                                   // further groups: load them now
+#pragma unroll
+            for (int c = 0; c < SC_GROUP; ++c) {
+                if (c0 + c >= cols.n) break;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int j = tid + i * RB_THREADS;
+                    val[c][i] = 0;
+                    if (j < cnt)
+                        val[c][i] = cols.bytes[c0 + c] == 8 ? ((const uint64_t *)cols.in[c0 + c])[lo + j]
+                                                            : (uint64_t)((const uint32_t *)cols.in[c0 + c])[lo + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < SC_GROUP; ++c) {
+            if (c0 + c >= cols.n) break;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) s_stage[tid + i * RB_THREADS] = val[c][i];
+            __syncthreads();
+            if (cols.bytes[c0 + c] == 8) {
+                uint64_t *out = (uint64_t *)cols.out[c0 + c];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) put_out<uint64_t, NT>(&out[dst[i]], s_stage[src[i]]);
+            } else {
+                uint32_t *out = (uint32_t *)cols.out[c0 + c];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) put_out<uint32_t, NT>(&out[dst[i]], (uint32_t)s_stage[src[i]]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Pass 4 of the fused step: the tile is already in sorted order, so slot j of
+// the tile goes to run_dest[run(j)] + (j - run_start): contiguous reads and
+// run-contiguous writes, no staging.
+template <int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_scatter_sorted(int64_t n, RebinScratch sc, Cols cols,
+                                                              uint32_t *status) {
+    constexpr int TILE = RB_THREADS * IPT;
+    __shared__ uint16_t s_rstart[TILE + 1];
+    __shared__ uint32_t s_rdest[TILE];
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t lo = tile * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+    const uint32_t nr = sc.tile_nruns[tile];
+    const uint32_t ri0 = sc.run_info[lo + tid];
+    const uint32_t rd0 = sc.run_dest[lo + tid];
+    uint64_t val[4][IPT];
+    const int ng = min(cols.n, 4);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= ng) break;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int j = tid + i * RB_THREADS;
+            val[c][i] = 0;
+            if (j < cnt)
+                val[c][i] = cols.bytes[c] == 8 ? ((const uint64_t *)cols.in[c])[lo + j]
+                                               : (uint64_t)((const uint32_t *)cols.in[c])[lo + j];
+        }
+    }
+    if ((uint32_t)tid < nr) {
+        s_rstart[tid] = (uint16_t)(ri0 & 0xffffu);
+        s_rdest[tid] = rd0;
+    }
+    for (uint32_t q = tid + RB_THREADS; q < nr; q += RB_THREADS) {
+        s_rstart[q] = (uint16_t)(sc.run_info[lo + q] & 0xffffu);
+        s_rdest[q] = sc.run_dest[lo + q];
+    }
+    if (tid == 0) s_rstart[nr] = (uint16_t)min(cnt, 0xffff);
+    __syncthreads();
+    uint32_t dst[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int j = tid + i * RB_THREADS;
+        dst[i] = 0xffffffffu;
+        if (j < cnt) {
+            uint32_t a = 0, b = nr - 1;
+            while (a < b) {
+                const uint32_t m = (a + b + 1) >> 1;
+                if (s_rstart[m] <= j) a = m; else b = m - 1;
+            }
+            dst[i] = s_rdest[a] + (uint32_t)(j - s_rstart[a]);
+            if (dst[i] >= (uint32_t)n) {
+                dst[i] = 0xffffffffu;
+                flag_status(status, PIC_DEV_RANGE);
+            }
+        }
+    }
+    for (int c0 = 0; c0 < cols.n; c0 += 4) {
+        if (c0 > 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c0 + c >= cols.n) break;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int j = tid + i * RB_THREADS;
+                    val[c][i] = 0;
+                    if (j < cnt)
+                        val[c][i] = cols.bytes[c0 + c] == 8 ? ((const uint64_t *)cols.in[c0 + c])[lo + j]
+                                                            : (uint64_t)((const uint32_t *)cols.in[c0 + c])[lo + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c0 + c >= cols.n) break;
+            if (cols.bytes[c0 + c] == 8) {
+                uint64_t *out = (uint64_t *)cols.out[c0 + c];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) out[dst[i]] = val[c][i];
+            } else {
+                uint32_t *out = (uint32_t *)cols.out[c0 + c];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (dst[i] != 0xffffffffu) out[dst[i]] = (uint32_t)val[c][i];
+            }
+        }
+    }
+}
+
+// Zero the per-call counters and, when the input is sorted, find the old bins
+// covering each tile (one kernel instead of two).
+__global__ void k_rebin_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_start, int64_t n_bins, int64_t n,
+                             int tile, RebinScratch sc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = gid; i < n_zero; i += stride) zero[i] = 0;
+    if (!old_start) return;
+    const int64_t n_tiles = (n + tile - 1) / tile;
+    for (int64_t b = gid; b < n_bins; b += stride) {
+        const int64_t s0 = max(old_start[b], (int64_t)0), s1 = min(old_start[b + 1], n);
+        if (s1 <= s0) continue;
+        for (int64_t t = (s0 + tile - 1) / tile; t * tile < s1; ++t) sc.tile_bin[2 * t] = (uint32_t)b;
+        for (int64_t t = s0 / tile; t < n_tiles; ++t) {
+            const int64_t last = min((t + 1) * tile, n) - 1;
+            if (last >= s1) break;
+            if (last >= s0) sc.tile_bin[2 * t + 1] = (uint32_t)(b + 1);
+        }
     }
 }
 
 // ----------------------------------------------------------------- deposit
 
-template <int N>
-__device__ __forceinline__ void wave_sum(double (&acc)[N]) {
+// Sum over groups of G consecutive lanes (butterfly inside the group, fixed
+// order, so the result is the same on every run).
+template <int G, int N>
+__device__ __forceinline__ void group_sum(double (&acc)[N]) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
+    for (int o = G >> 1; o > 0; o >>= 1)
 #pragma unroll
         for (int c = 0; c < N; ++c) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], o, 64));
 }
 
-// A wavefront per bin: PIT sums weights per leaf corner, PIDT per stencil slot
-// of the owning vertex.  With per-particle charges the terms are q_p w_c,
-// otherwise w_c (the uniform charge is applied per vertex).
-template <int D, int SCHEME, bool REG>
+// Accumulate one particle's restriction weights: PIT per leaf corner, PIDT
+// per stencil slot of the owning vertex.
+template <int D, int SCHEME, bool REG, int NS>
+__device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp, int e, double s, uint32_t su,
+                                            double rinv, double qp, bool use_q, double (&acc)[NS]) {
+    uint32_t bad = 0;
+    Axis ax[D];
+    uint32_t a[D];
+    double f[D], g[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
+        const uint32_t I = ax[k].T >> 1;
+        a[k] = REG ? I : div_pow3(I, e);
+        f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
+        g[k] = __dsub_rn(1.0, f[k]);
+    }
+    if (SCHEME == PIC_PIT) {
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) {
+            double wc = (c & 1) ? f[0] : g[0];
+#pragma unroll
+            for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
+            acc[c] = __dadd_rn(acc[c], use_q ? __dmul_rn(qp, wc) : wc);
+        }
+    } else {
+        // The owner is the corner nearest to the particle.  Per axis the
+        // particle's two corner weights (g, f) land on stencil offsets {0,+1}
+        // (owner below) or {-1,0} (owner above); the 3^d slot weights are the
+        // tensor product of these per-axis triples, so every slot is updated
+        // branch-free (absent ones with +0).
+        double u[D][3];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const bool up = ax[k].T >= (2u * a[k] + 1u) * su;
+            u[k][0] = up ? g[k] : 0.0;
+            u[k][1] = up ? f[k] : g[k];
+            u[k][2] = up ? 0.0 : f[k];
+        }
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            double wc = u[0][sl % 3];
+            wc = __dmul_rn(wc, u[1][(sl / 3) % 3]);
+            if (D == 3) wc = __dmul_rn(wc, u[D - 1][sl / 9]);
+            acc[sl] = __dadd_rn(acc[sl], use_q ? __dmul_rn(qp, wc) : wc);
+        }
+    }
+}
+
+// G lanes per bin (64/G bins per wavefront).  A bin's particles are taken in
+// batches of G*K; all loads of a batch are issued before the first is used,
+// so a bin of up to G*K particles costs one memory latency after its offsets
+// arrive.  With per-particle charges the terms are q_p w_c, otherwise w_c
+// (the uniform charge is applied per vertex).
+template <int D, int SCHEME, bool REG, int G, int K>
 __global__ __launch_bounds__(256) void k_deposit_bins(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
                                                       const int64_t *bin_start, int64_t n_bins, const double *q,
                                                       double *partial) {
     constexpr int NS = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < n_bins; b += waves) {
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / G) + (threadIdx.x / G); b < n_bins; b += groups) {
         int ii = 0;
         if (t.n_inst > 1) ii = SCHEME == PIC_PIT ? t.leaf_inst[b] : t.pidt_inst[b];
         const DevInst &in = t.n_inst > 1 ? t.inst[ii] : in0;
@@ -751,52 +1180,22 @@ __global__ __launch_bounds__(256) void k_deposit_bins(DevTree t, DevInst in0, F6
             if (lane == 0) flag_status(t.status, PIC_DEV_RANGE);
             p0 = p1 = 0;
         }
-        for (int64_t p = p0 + lane; p < p1; p += 64) {
-            uint32_t bad = 0;
-            Axis ax[D];
-            uint32_t a[D];
-            double f[D], g[D];
+        for (int64_t base = p0; base < p1; base += G * K) {
+            double xs[K][D], qs[K];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                ax[k] = scale_axis(P.x[k][p], in.Sd, in.S, bad);
-                const uint32_t I = ax[k].T >> 1;
-                a[k] = REG ? I : div_pow3(I, e);
-                f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
-                g[k] = __dsub_rn(1.0, f[k]);
+            for (int k = 0; k < K; ++k) {
+                const int64_t p = base + lane + G * k;
+                const bool ok = p < p1;
+#pragma unroll
+                for (int d = 0; d < D; ++d) xs[k][d] = ok ? P.x[d][p] : 0.0;
+                qs[k] = (ok && q) ? q[p] : 1.0;
             }
-            const double qp = q ? q[p] : 1.0;
-            if (SCHEME == PIC_PIT) {
 #pragma unroll
-                for (int c = 0; c < (1 << D); ++c) {
-                    double wc = (c & 1) ? f[0] : g[0];
-#pragma unroll
-                    for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
-                    acc[c] = __dadd_rn(acc[c], q ? __dmul_rn(qp, wc) : wc);
-                }
-            } else {
-                // The owner is the corner nearest to the particle.  Per axis the
-                // particle's two corner weights (g, f) land on stencil offsets
-                // {0,+1} (owner below) or {-1,0} (owner above); the 3^d slot
-                // weights are the tensor product of these per-axis triples, so
-                // every slot is updated branch-free (absent ones with +0).
-                double u[D][3];
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const bool up = ax[k].T >= (2u * a[k] + 1u) * su;
-                    u[k][0] = up ? g[k] : 0.0;
-                    u[k][1] = up ? f[k] : g[k];
-                    u[k][2] = up ? 0.0 : f[k];
-                }
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl) {
-                    double wc = u[0][sl % 3];
-                    wc = __dmul_rn(wc, u[1][(sl / 3) % 3]);
-                    if (D == 3) wc = __dmul_rn(wc, u[D - 1][sl / 9]);
-                    acc[sl] = __dadd_rn(acc[sl], q ? __dmul_rn(qp, wc) : wc);
-                }
-            }
+            for (int k = 0; k < K; ++k)
+                if (base + lane + G * k < p1)
+                    deposit_one<D, SCHEME, REG, NS>(in, xs[k], e, s, su, rinv, qs[k], q != nullptr, acc);
         }
-        wave_sum<NS>(acc);
+        group_sum<G, NS>(acc);
         if (lane == 0) {
 #pragma unroll
             for (int c = 0; c < NS; ++c) partial[b * NS + c] = acc[c];
@@ -979,25 +1378,26 @@ static int64_t n_bins_of(const pic_tree *t, int scheme) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
-    size_t perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
+    size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
         list, scan_state, scan_ctr, total;
 };
 
-static RebinLayout rebin_layout(int64_t n, int64_t n_bins) {
+static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     RebinLayout L{};
-    const int64_t tiles = (n + RB_TILE - 1) / RB_TILE;
-    const int64_t slots = tiles * RB_TILE;
+    const int64_t tiles = (n + tile - 1) / tile;
+    const int64_t slots = tiles * tile;
     const int64_t keys = 2 * n_bins;
     const int64_t scan_blocks = (keys + SCAN_TILE - 1) / SCAN_TILE;
     size_t o = 0;
+    L.tile_bin = o; o = align256(o + tiles * 8);
     L.perm = o; o = align256(o + slots * 2);
     L.run_key = o; o = align256(o + slots * 4);
     L.run_info = o; o = align256(o + slots * 4);
     L.run_dest = o; o = align256(o + slots * 4);
     L.tile_nruns = o; o = align256(o + tiles * 4);
-    L.key_cnt = o; o = align256(o + keys * 4);      // key_cnt, key_nruns, key_fill contiguous:
-    L.key_nruns = o; o = align256(o + keys * 4);    // one fill clears all three
-    L.key_fill = o; o = align256(o + keys * 4);
+    L.key_cnt = o; o = align256(o + keys * 4);      // key_cnt, key_nruns, key_fill, the scan state and
+    L.key_nruns = o; o = align256(o + keys * 4);    // the block counter are contiguous: one fill clears
+    L.key_fill = o; o = align256(o + keys * 4);     // them all
     L.scan_state = o; o = align256(o + scan_blocks * 8);
     L.scan_ctr = o; o = align256(o + 4);
     L.key_base = o; o = align256(o + keys * 4);
@@ -1007,17 +1407,47 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins) {
     return L;
 }
 
+Tuning g_tune;
+
 size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme) {
-    return rebin_layout(n, n_bins_of(t, scheme)).total;
+    // large enough for every supported tile size
+    const int64_t nb = n_bins_of(t, scheme);
+    return std::max(rebin_layout(n, nb, 2048).total, rebin_layout(n, nb, 4096).total);
 }
 
-hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t *new_bin, const int64_t *old_start,
-                        const Cols &cols, int64_t *new_start, void *scratch, size_t scratch_bytes, hipStream_t s) {
-    const int64_t n_bins = n_bins_of(t, scheme);
-    const RebinLayout L = rebin_layout(n, n_bins);
-    if (scratch_bytes < L.total) return hipErrorInvalidValue;
-    char *base = (char *)scratch;
+template <int IPT>
+static void launch_tiles(int radix, dim3 g, hipStream_t s, const uint32_t *nb, const int64_t *os, int64_t n,
+                         uint32_t n_bins, const RebinScratch &sc, uint32_t *status) {
+    if (radix == 5) PIC_LAUNCH("rebin_tiles", (k_rebin_tiles<IPT, 5>), g, dim3(RB_THREADS), 0, s, nb, os, n, n_bins, sc, status);
+    else PIC_LAUNCH("rebin_tiles", (k_rebin_tiles<IPT, 4>), g, dim3(RB_THREADS), 0, s, nb, os, n, n_bins, sc, status);
+}
+
+template <int IPT, int MODE, bool NT>
+static void launch_scatter_g(dim3 g, hipStream_t s, int64_t n, const RebinScratch &sc, const Cols &cols,
+                             uint32_t *status) {
+    switch (g_tune.scatter_group) {
+        case 1: PIC_LAUNCH("rebin_scatter", (k_rebin_scatter<IPT, MODE, NT, 1>), g, dim3(RB_THREADS), 0, s, n, sc, cols, status); break;
+        case 2: PIC_LAUNCH("rebin_scatter", (k_rebin_scatter<IPT, MODE, NT, 2>), g, dim3(RB_THREADS), 0, s, n, sc, cols, status); break;
+        default: PIC_LAUNCH("rebin_scatter", (k_rebin_scatter<IPT, MODE, NT, 4>), g, dim3(RB_THREADS), 0, s, n, sc, cols, status); break;
+    }
+}
+
+template <int IPT>
+static void launch_scatter(int mode, dim3 g, hipStream_t s, int64_t n, const RebinScratch &sc, const Cols &cols,
+                           uint32_t *status) {
+    const bool nt = g_tune.scatter_nt != 0;
+    if (mode == 1) {
+        if (nt) launch_scatter_g<IPT, 1, true>(g, s, n, sc, cols, status);
+        else launch_scatter_g<IPT, 1, false>(g, s, n, sc, cols, status);
+    } else {
+        if (nt) launch_scatter_g<IPT, 0, true>(g, s, n, sc, cols, status);
+        else launch_scatter_g<IPT, 0, false>(g, s, n, sc, cols, status);
+    }
+}
+
+static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     RebinScratch sc;
+    sc.tile_bin = (uint32_t *)(base + L.tile_bin);
     sc.perm = (uint16_t *)(base + L.perm);
     sc.run_key = (uint32_t *)(base + L.run_key);
     sc.run_info = (uint32_t *)(base + L.run_info);
@@ -1031,25 +1461,117 @@ hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t
     sc.list = (uint32_t *)(base + L.list);
     sc.scan_state = (uint64_t *)(base + L.scan_state);
     sc.scan_ctr = (uint32_t *)(base + L.scan_ctr);
+    return sc;
+}
+
+// The part of a re-bin that follows the tile sort: per-key scan, run lists,
+// run placement.
+static void launch_rebin_middle(const pic_tree *t, int64_t n, int64_t n_bins, int tile, const RebinScratch &sc,
+                                int64_t *new_start, hipStream_t s) {
     const int64_t keys = 2 * n_bins;
-    const int64_t tiles = (n + RB_TILE - 1) / RB_TILE;
-    // counters, scan flags and the block counter start at zero (fill kernel,
-    // not a memset node, so the sequence can be captured in a graph)
-    const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
-    PIC_LAUNCH("rebin_clear", k_fill_u32, dim3(grid_for(zero_words, 256, 4096)), dim3(256), 0, s,
-                       (uint32_t *)(base + L.key_cnt), zero_words, 0u);
-    if (n > 0)
-        PIC_LAUNCH("rebin_tiles", k_rebin_tiles, dim3(tiles), dim3(RB_THREADS), 0, s, new_bin, old_start, n,
-                           (uint32_t)n_bins, sc, t->dt.status);
+    const int64_t tiles = (n + tile - 1) / tile;
     const int64_t scan_blocks = (keys + SCAN_TILE - 1) / SCAN_TILE;
     PIC_LAUNCH("rebin_scan", k_rebin_scan, dim3(scan_blocks), dim3(256), 0, s, (uint32_t)keys, (uint32_t)n_bins, n, sc,
-                       new_start, t->dt.status);
+               new_start, t->dt.status);
     if (n > 0) {
-        PIC_LAUNCH("rebin_lists", k_rebin_lists, dim3(tiles), dim3(256), 0, s, sc);
-        PIC_LAUNCH("rebin_place", k_rebin_place, dim3(tiles), dim3(256), 0, s, sc);
-        PIC_LAUNCH("rebin_scatter", k_rebin_scatter, dim3(tiles), dim3(RB_THREADS), 0, s, n, sc, cols, t->dt.status);
+        PIC_LAUNCH("rebin_lists", k_rebin_lists, dim3(tiles), dim3(256), 0, s, sc, tile);
+        PIC_LAUNCH("rebin_place", k_rebin_place, dim3(grid_for(keys, 16, 1 << 16)), dim3(256), 0, s, sc, (uint32_t)keys);
+    }
+}
+
+hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t *new_bin, const int64_t *old_start,
+                        const Cols &cols, int64_t *new_start, void *scratch, size_t scratch_bytes, hipStream_t s) {
+    const int64_t n_bins = n_bins_of(t, scheme);
+    const int ipt = g_tune.rebin_ipt;
+    const int tile = RB_THREADS * ipt;
+    const RebinLayout L = rebin_layout(n, n_bins, tile);
+    if (scratch_bytes < L.total) return hipErrorInvalidValue;
+    char *base = (char *)scratch;
+    const RebinScratch sc = bind_scratch(L, base);
+    const int64_t tiles = (n + tile - 1) / tile;
+    // counters, scan flags and the block counter start at zero (a kernel, not a
+    // memset node, so the sequence can be captured in a graph); the same kernel
+    // finds the old bins covering each tile
+    const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
+    PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(std::max(zero_words, n_bins), 256, 4096)), dim3(256), 0,
+               s, (uint32_t *)(base + L.key_cnt), zero_words, n > 0 ? old_start : nullptr, n_bins, n, tile, sc);
+    if (n > 0) {
+        if (ipt == 8) launch_tiles<8>(g_tune.rebin_radix, dim3(tiles), s, new_bin, old_start, n, (uint32_t)n_bins, sc, t->dt.status);
+        else launch_tiles<16>(g_tune.rebin_radix, dim3(tiles), s, new_bin, old_start, n, (uint32_t)n_bins, sc, t->dt.status);
+    }
+    launch_rebin_middle(t, n, n_bins, tile, sc, new_start, s);
+    if (n > 0) {
+        if (ipt == 8) launch_scatter<8>(g_tune.scatter_mode, dim3(tiles), s, n, sc, cols, t->dt.status);
+        else launch_scatter<16>(g_tune.scatter_mode, dim3(tiles), s, n, sc, cols, t->dt.status);
     }
     return hipGetLastError();
+}
+
+size_t deposit_scratch_bytes(const pic_tree *t, int scheme);
+hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p, const int64_t *bin_start,
+                          const double *q, double q_uniform, double *rho, void *scratch, size_t scratch_bytes,
+                          hipStream_t s);
+
+#define PIC_DISPATCH_PS(D, SCH, REG, MULTI)                                                                  \
+    PIC_LAUNCH("push_sort", (k_push_sort<D, SCH, REG, MULTI, 8>), dim3(tiles), dim3(RB_THREADS), 0, s, t->dt,     \
+               t->inst0, P, n, qmdt, dt, qa, da, in->inst_start_dev, old_start, (uint32_t)n_bins, sc, extra)
+
+hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
+                       const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,
+                       pic_particles *out, int64_t *new_start, int q_col, double q_uniform, double *rho,
+                       void *scratch, size_t scratch_bytes, hipStream_t s) {
+    const int64_t n = in->n;
+    const int64_t n_bins = n_bins_of(t, scheme);
+    const int tile = RB_THREADS * 8;
+    const RebinLayout L = rebin_layout(n, n_bins, tile);
+    if (scratch_bytes < L.total || scratch_bytes < deposit_scratch_bytes(t, scheme)) return hipErrorInvalidValue;
+    char *base = (char *)scratch;
+    const RebinScratch sc = bind_scratch(L, base);
+    const int64_t tiles = (n + tile - 1) / tile;
+    const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
+    PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(std::max(zero_words, n_bins), 256, 4096)), dim3(256), 0,
+               s, (uint32_t *)(base + L.key_cnt), zero_words, n > 0 ? old_start : nullptr, n_bins, n, tile, sc);
+    if (n > 0) {
+        F64Ptrs P = make_ptrs(t, in, E, nullptr);
+        const double *qa = pp ? pp->qmdt_dev : nullptr;
+        const double *da = pp ? pp->dt_dev : nullptr;
+        const bool multi = t->n_inst > 1, reg = t->all_regular;
+        if (t->dim == 2) {
+            if (scheme == PIC_PIT) {
+                if (multi) { if (reg) PIC_DISPATCH_PS(2, 0, true, true); else PIC_DISPATCH_PS(2, 0, false, true); }
+                else { if (reg) PIC_DISPATCH_PS(2, 0, true, false); else PIC_DISPATCH_PS(2, 0, false, false); }
+            } else {
+                if (multi) { if (reg) PIC_DISPATCH_PS(2, 1, true, true); else PIC_DISPATCH_PS(2, 1, false, true); }
+                else { if (reg) PIC_DISPATCH_PS(2, 1, true, false); else PIC_DISPATCH_PS(2, 1, false, false); }
+            }
+        } else {
+            if (scheme == PIC_PIT) {
+                if (multi) { if (reg) PIC_DISPATCH_PS(3, 0, true, true); else PIC_DISPATCH_PS(3, 0, false, true); }
+                else { if (reg) PIC_DISPATCH_PS(3, 0, true, false); else PIC_DISPATCH_PS(3, 0, false, false); }
+            } else {
+                if (multi) { if (reg) PIC_DISPATCH_PS(3, 1, true, true); else PIC_DISPATCH_PS(3, 1, false, true); }
+                else { if (reg) PIC_DISPATCH_PS(3, 1, true, false); else PIC_DISPATCH_PS(3, 1, false, false); }
+            }
+        }
+    }
+    launch_rebin_middle(t, n, n_bins, tile, sc, new_start, s);
+    if (n > 0) {
+        Cols cols{};
+        cols.n = 0;
+        for (int k = 0; k < t->dim; ++k) {
+            cols.in[cols.n] = in->x[k]; cols.out[cols.n] = out->x[k]; cols.bytes[cols.n++] = 8;
+        }
+        for (int k = 0; k < t->dim; ++k) {
+            cols.in[cols.n] = in->v[k]; cols.out[cols.n] = out->v[k]; cols.bytes[cols.n++] = 8;
+        }
+        for (int c = 0; c < extra.n; ++c) {
+            cols.in[cols.n] = extra.in[c]; cols.out[cols.n] = extra.out[c]; cols.bytes[cols.n++] = extra.bytes[c];
+        }
+        PIC_LAUNCH("scatter_sorted", k_scatter_sorted<8>, dim3(tiles), dim3(RB_THREADS), 0, s, n, sc, cols,
+                   t->dt.status);
+    }
+    const double *q = q_col >= 0 ? (const double *)extra.out[q_col] : nullptr;
+    return launch_deposit(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);
 }
 
 size_t deposit_scratch_bytes(const pic_tree *t, int scheme) {
@@ -1057,10 +1579,15 @@ size_t deposit_scratch_bytes(const pic_tree *t, int scheme) {
     return align256((size_t)n_bins_of(t, scheme) * ns * sizeof(double));
 }
 
+#define PIC_DEP_BINS(D, SCH, REG, G)                                                                          \
+    PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 256 / G>), dim3(grid_for(n_bins, 256 / G, 1 << 18)), \
+               dim3(256), 0, s, t->dt, t->inst0, P, p->n, bin_start, n_bins, q, partial)
+
 #define PIC_DISPATCH_DEP(D, SCH, REG)                                                                         \
     do {                                                                                                     \
-        PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG>), dim3(grid_for(n_bins, 4, 1 << 18)), dim3(256), 0, s, \
-                           t->dt, t->inst0, P, p->n, bin_start, n_bins, q, partial);                               \
+        if (g_tune.deposit_lanes == 16) PIC_DEP_BINS(D, SCH, REG, 16);                                       \
+        else if (g_tune.deposit_lanes == 32) PIC_DEP_BINS(D, SCH, REG, 32);                                  \
+        else PIC_DEP_BINS(D, SCH, REG, 64);                                                                  \
         PIC_LAUNCH("deposit_vertices", (k_deposit_vertices<D, SCH, REG>), dim3(grid_for(n_vtx, 256, 1 << 16)), dim3(256), \
                            0, s, t->dt, t->inst0, partial, n_vtx, q ? 1 : 0, q_uniform, rho);                 \
     } while (0)

@@ -245,3 +245,88 @@ def test_forest_locate_and_step_match_oracle_per_instance():
                        o.deposit(xs[:, p0:p0 + w.n], None, -1.0))
             p0 += w.n
         assert t.status_sync() == 0
+
+
+KNOB_SETS = ([dict(rebin_tile=t, rebin_radix=r, scatter_mode=m, scatter_nt=nt)
+              for t in (2048, 4096) for r in (4, 5) for m in (0, 1) for nt in (0, 1)]
+             + [dict(scatter_group=g, deposit_lanes=d) for g in (1, 2, 4) for d in (16, 32, 64)])
+
+
+@pytest.mark.parametrize("knobs", KNOB_SETS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
+@pytest.mark.parametrize("name,scheme", [("config1", 0), ("small_adaptive", 1)])
+def test_every_launch_shape_gives_the_same_step(name, scheme, knobs):
+    dev = _dev()
+    saved = pic.tuning()
+    try:
+        for k, v in knobs.items():
+            pic.tune(k, v)
+        wl = W.by_name(name)
+        o = oracle.OracleTree(wl.tree)
+        t = _tree(wl.tree)
+        rng = np.random.default_rng(17)
+        st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, ids=np.arange(wl.n), device=dev)
+        st.initial_sort()
+        xs, vs, qs, start, perm = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+        E = _field(o, wl, rng, "random")
+        st.step(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+        r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+        assert np.array_equal(st.ids.cpu().numpy(), perm[r["perm"]])
+        assert np.array_equal(st.x.cpu().numpy(), r["x"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        assert t.status_sync() == 0
+    finally:
+        for k, v in saved.items():
+            pic.tune(k, v)
+
+
+@pytest.mark.parametrize("kind", ["random", "physical"])
+@pytest.mark.parametrize("name,scheme", CASES)
+def test_fused_step_matches_oracle(name, scheme, kind):
+    """pic_step (fused kernels) against the oracle over three teacher-forced steps."""
+    dev = _dev()
+    wl = W.by_name(name)
+    o = oracle.OracleTree(wl.tree)
+    t = _tree(wl.tree)
+    rng = np.random.default_rng(98)
+    st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, ids=np.arange(wl.n, dtype=np.int64), device=dev)
+    st.initial_sort()
+    xs, vs, qs, start, perm = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+    ids = perm
+    for it in range(3):
+        E = _field(o, wl, rng, kind)
+        st.x.copy_(torch.from_numpy(xs))
+        st.v.copy_(torch.from_numpy(vs))
+        st.step_fused(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+        r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"]), f"offsets differ at step {it}"
+        ids = ids[r["perm"]]
+        assert np.array_equal(st.ids.cpu().numpy(), ids), f"order differs at step {it}"
+        assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+        if qs is not None:
+            assert np.array_equal(st.q.cpu().numpy(), r["q"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
+    assert t.status_sync() == 0
+
+
+@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 5 * 2048 + 3])
+def test_fused_and_separate_calls_agree_bitwise(n):
+    dev = _dev()
+    rng = np.random.default_rng(n)
+    spec = W.disc_tree(2, 2, 4)
+    t = _tree(spec)
+    x, v = rng.random((2, n)), rng.standard_normal((2, n)) * 0.05
+    E = torch.tensor(W.random_field(rng, 2, t.n_vertices, 0.3), device=dev)
+    outs = []
+    for fused in (False, True):
+        st = pic.Stepper(t, 1, x, v, ids=np.arange(n), device=dev)
+        st.initial_sort()
+        for _ in range(2):
+            (st.step_fused if fused else st.step)(E, -0.7, 0.7, q_uniform=-1.0)
+        torch.cuda.synchronize()
+        outs.append([a.cpu().numpy().copy() for a in (st.x, st.v, st.ids, st.start, st.rho)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

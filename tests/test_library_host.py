@@ -136,3 +136,20 @@ def test_calls_check_arguments_before_the_device():
     assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, cols, w8, start, fake, need, None) == _capi.PIC_E_ARG
     assert L.pic_status_sync(t.handle, None) == _capi.PIC_E_STATE
     assert _capi.status_string(_capi.PIC_E_SCRATCH) == "scratch buffer too small"
+
+
+def test_tuning_knobs_accept_only_listed_values():
+    before = pic.tuning()
+    try:
+        for name, values in pic.TUNING_KNOBS.items():
+            for v in values:
+                pic.tune(name, v)
+                assert pic.tuning()[name] == v
+            with pytest.raises(pic.PicError):
+                pic.tune(name, 12345)
+        with pytest.raises(pic.PicError):
+            pic.tune("no_such_knob", 1)
+        assert _capi.lib().pic_tune_get(b"no_such_knob") == -1
+    finally:
+        for k, v in before.items():
+            pic.tune(k, v)
