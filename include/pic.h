@@ -310,7 +310,8 @@ pic_status pic_profile_enable(int32_t on);
  *                   the tile (default 0);
  *   "scatter_nt"    1 = non-temporal stores for the re-binned records (default 0);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
- *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64).
+ *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
+ *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048).
  * Every setting gives the same results; pic_scratch_bytes covers all of them.
  * Affects calls enqueued afterwards.  Unknown names or values: PIC_E_ARG
  * (pic_tune_get returns -1).

@@ -72,6 +72,27 @@ pic_status assemble(pic_tree *t) {
     t->n_vinc = (int64_t)vinc.size();
     t->n_vpinc = (int64_t)vpinc.size();
 
+    // Peano rank tables for the levels of regular instances (shared by
+    // instances of equal level), when a level's table is small enough
+    constexpr int64_t kMaxTab = int64_t(1) << 21;
+    std::vector<int64_t> tab_off(PIC_MAX_LEVEL + 1, -1);
+    std::vector<uint32_t> ptab;
+    for (int i = 0; i < ni; ++i) {
+        const HostInst &h = t->inst[i];
+        if (!h.regular || tab_off[h.L] >= 0) continue;
+        int64_t cells = 1;
+        for (int k = 0; k < dim; ++k) cells *= (int64_t)h.S;
+        if (cells > kMaxTab) continue;
+        tab_off[h.L] = (int64_t)ptab.size();
+        ptab.resize(ptab.size() + (size_t)cells);
+        uint32_t *dst = ptab.data() + tab_off[h.L];
+        const uint32_t S = (uint32_t)h.S;
+        for (int64_t c = 0; c < cells; ++c) {
+            uint32_t a[3] = {(uint32_t)(c % S), (uint32_t)((c / S) % S), (uint32_t)(c / ((int64_t)S * S))};
+            dst[c] = dim == 2 ? peano_low<2>(a, h.L) : peano_low<3>(a, h.L);
+        }
+    }
+
     size_t o = 0;
     t->o_status = o; o = align256(o + 256);
     t->o_inst = o; o = align256(o + (size_t)ni * sizeof(DevInst));
@@ -89,6 +110,7 @@ pic_status assemble(pic_tree *t) {
     t->o_vinc = o; o = align256(o + (size_t)vinc.size() * 4);
     t->o_vpptr = o; o = align256(o + (size_t)(NV + 1) * 4);
     t->o_vpinc = o; o = align256(o + (size_t)vpinc.size() * 4);
+    t->o_ptab = o; o = align256(o + ptab.size() * 4);
     t->device_bytes = (int64_t)o;
     t->image.assign(o, 0);
 
@@ -108,6 +130,7 @@ pic_status assemble(pic_tree *t) {
         d.pidt_off = (int32_t)t->pidt_off[i];
         d.n_pidt = (int32_t)h.pidt_key.size();
         d.lds_nodes = (int32_t)std::min<int64_t>((int64_t)h.node_child.size(), PIC_LDS_NODES);
+        d.ptab = h.regular ? (int32_t)tab_off[h.L] : -1;
         d.Sd = (double)h.S;
         for (int l = 0; l <= h.L; ++l) d.rinv[l] = 1.0 / (double)pow3_u64(h.L - l);
         // node table with forest-wide indices
@@ -141,6 +164,9 @@ pic_status assemble(pic_tree *t) {
     put(t->image, t->o_vinc, vinc.data(), (int64_t)vinc.size());
     put(t->image, t->o_vpptr, vpptr.data(), NV + 1);
     put(t->image, t->o_vpinc, vpinc.data(), (int64_t)vpinc.size());
+    put(t->image, t->o_ptab, ptab.data(), (int64_t)ptab.size());
+    t->reg_kernels = 1;
+    for (int i = 0; i < ni; ++i) t->reg_kernels &= di[i].regular && di[i].ptab >= 0;
     t->inst0 = di[0];
     (void)nsten;
     return PIC_OK;
@@ -171,6 +197,7 @@ void bind(pic_tree *t) {
     d.vinc = (const int32_t *)(b + t->o_vinc);
     d.vpinc_ptr = (const int32_t *)(b + t->o_vpptr);
     d.vpinc = (const int32_t *)(b + t->o_vpinc);
+    d.peano_tab = (const uint32_t *)(b + t->o_ptab);
     d.status = (uint32_t *)(b + t->o_status);
 }
 
@@ -465,6 +492,9 @@ pic_status pic_tune_set(const char *name, int64_t value) {
     } else if (k == "deposit_lanes") {
         if (value != 16 && value != 32 && value != 64) return PIC_E_ARG;
         g_tune.deposit_lanes = (int)value;
+    } else if (k == "step_tile") {
+        if (value != 1024 && value != 2048) return PIC_E_ARG;
+        g_tune.step_ipt = (int)(value / 256);
     } else if (k == "scatter_nt") {
         if (value != 0 && value != 1) return PIC_E_ARG;
         g_tune.scatter_nt = (int)value;
@@ -483,6 +513,7 @@ int64_t pic_tune_get(const char *name) {
     if (k == "scatter_nt") return g_tune.scatter_nt;
     if (k == "scatter_group") return g_tune.scatter_group;
     if (k == "deposit_lanes") return g_tune.deposit_lanes;
+    if (k == "step_tile") return 256 * (int64_t)g_tune.step_ipt;
     return -1;
 }
 

@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -41,6 +42,7 @@ uint64_t host_peano(int dim, const uint32_t *a, int nd);
 // The opaque tree object of the C ABI.
 struct pic_tree {
     int32_t dim = 0, n_inst = 0, all_regular = 1, max_level = 0;
+    int32_t reg_kernels = 0;  // every instance regular with a Peano table: arithmetic kernels apply
     std::vector<pic::HostInst> inst;
     std::vector<int64_t> leaf_off, vtx_off, pidt_off, node_off;  // n_inst + 1 each
     std::vector<uint8_t> image;        // host copy of the device image
@@ -48,7 +50,7 @@ struct pic_tree {
     // byte offsets of the tables inside the image
     int64_t o_status = 0, o_inst = 0, o_node = 0, o_ubase = 0, o_umeta = 0, o_llev = 0, o_lvtx = 0,
             o_lpidt = 0, o_plev = 0, o_linst = 0, o_pinst = 0, o_vinst = 0, o_vptr = 0, o_vinc = 0,
-            o_vpptr = 0, o_vpinc = 0;
+            o_vpptr = 0, o_vpinc = 0, o_ptab = 0;
     int64_t n_nodes = 0, n_vinc = 0, n_vpinc = 0;
     void *dev = nullptr;               // bound device buffer (caller-owned)
     pic::DevTree dt{};                 // device view, valid once uploaded
@@ -101,6 +103,7 @@ struct Tuning {
     int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
     int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
     int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
+    int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
 };
 extern Tuning g_tune;
 hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,

@@ -94,7 +94,7 @@ struct DevInst {
     int32_t vtx_off, n_vtx;
     int32_t pidt_off, n_pidt;
     int32_t lds_nodes;  // leading descent entries of this instance held in LDS (single tree)
-    int32_t pad0;
+    int32_t ptab;       // regular instances: offset of the Peano rank table of their level, else -1
     double Sd;          // (double)S
     double rinv[PIC_MAX_LEVEL + 1];  // fl(1 / 3^(L-l)) indexed by leaf level l
 };
@@ -119,6 +119,7 @@ struct DevTree {
     const int32_t *vinc;
     const int32_t *vpinc_ptr;   // n_vtx + 1: CSR vertex -> (pidt bin * 3^d + stencil slot), ascending
     const int32_t *vpinc;
+    const uint32_t *peano_tab;  // per level of regular instances: Peano rank of finest cell c0 + S c1 (+ S^2 c2)
     uint32_t *status;           // sticky device status word
 };
 

@@ -40,6 +40,15 @@ __device__ __forceinline__ void flag_status(uint32_t *status, uint32_t bit) {
     atomicOr(status, bit);
 }
 
+// Load base[idx] with a 32-bit element offset from a wavefront-uniform base
+// (a scalar base plus a 32-bit vector offset, no 64-bit address arithmetic).
+// Offsets stay below 2^32 bytes for every table and field array (the tree
+// builder caps vertex and leaf counts).
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t idx) {
+    return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
+}
+
 // Scaled coordinate of one axis.  y = fl(x * S) is the only rounding on the
 // way to the cell; T = floor(2y) resolves half cells (dual-cell faces).  The
 // clamp keeps indices in range for malformed input (which is flagged).
@@ -56,6 +65,30 @@ __device__ __forceinline__ Axis scale_axis(double x, double Sd, int S, uint32_t 
     t = fmin(fmax(t, 0.0), (double)(2 * S - 1));  // fmax drops NaN
     a.T = (uint32_t)t;
     return a;
+}
+
+// The same for a position just wrapped into [0,1): fl(x S) < S there, so
+// T = floor(2y) <= 2S-1 without a clamp.  A NaN (from a non-finite velocity
+// or field) converts to cell 0 and is flagged.
+__device__ __forceinline__ Axis scale_wrapped(double x, double Sd, uint32_t &bad) {
+    if (x != x) bad |= PIC_DEV_NONFINITE;
+    Axis a;
+    a.y = __dmul_rn(x, Sd);
+    a.T = (uint32_t)floor(__dadd_rn(a.y, a.y));
+    return a;
+}
+
+// Peano rank of finest cell c of a regular instance: table lookup when the
+// level has a table (always, with TAB), else digit by digit.
+template <int D, bool TAB>
+__device__ __forceinline__ uint32_t regular_rank(const DevTree &t, const DevInst &in, const uint32_t *c) {
+    if (TAB || in.ptab >= 0) {
+        const uint32_t S = (uint32_t)in.S;
+        uint32_t idx = c[0] + __umul24(c[1], S);
+        if (D == 3) idx += __umul24(c[D - 1], __umul24(S, S));
+        return ld_off(t.peano_tab, (uint32_t)in.ptab + idx);
+    }
+    return peano_low<D>(c, in.L);
 }
 
 // Descent from the root to the leaf holding finest cell I.  Returns the
@@ -110,7 +143,7 @@ __device__ __forceinline__ uint32_t bin_of(const DevTree &t, const DevInst &in, 
         if (SCHEME == PIC_PIT) {
 #pragma unroll
             for (int k = 0; k < D; ++k) c[k] = ax[k].T >> 1;
-            return (uint32_t)in.leaf_off + peano_low<D>(c, in.L);
+            return (uint32_t)in.leaf_off + regular_rank<D, true>(t, in, c);
         } else {
             const uint32_t S = (uint32_t)in.S, half = (S - 1u) >> 1;
 #pragma unroll
@@ -121,7 +154,7 @@ __device__ __forceinline__ uint32_t bin_of(const DevTree &t, const DevInst &in, 
                 if (J >= S) J -= S;
                 c[k] = J;
             }
-            return (uint32_t)in.pidt_off + peano_low<D>(c, in.L);
+            return (uint32_t)in.pidt_off + regular_rank<D, true>(t, in, c);
         }
     } else {
         uint32_t I[D];
@@ -168,7 +201,7 @@ struct F64Ptrs {
 // push_one updates xv, vv in place, stores E_p when P.Ep[0] is set, and
 // returns the particle's new bin; non-finite or out-of-box input sets bits
 // in `bad`.
-template <int D, int SCHEME, bool REG>
+template <int D, int SCHEME, bool REG, bool EP = true>
 __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in, const F64Ptrs &P,
                                              const int32_t *lds, int lds_n, double (&xv)[D], double (&vv)[D],
                                              double qmdt, double dt, int64_t p, uint32_t &bad) {
@@ -178,42 +211,52 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
         if (!(vv[k] - vv[k] == 0.0)) bad |= PIC_DEV_NONFINITE;
     }
-    // leaf holding x: coordinates a, width s, corner vertex ids
-    uint32_t I[D], a[D];
+    // leaf holding x: corner vertex ids and the local coordinates f, g
+    uint32_t I[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) I[k] = ax[k].T >> 1;
-    int lev = in.L;
-    int32_t vid[1 << D];
+    uint32_t vid[1 << D];
+    double f[D], g[D];
     if (REG) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) a[k] = I[k];
+        // finest cell I: corner c is I + bits of c per axis, periodic, so the
+        // ids follow from the id of corner 0 by per-axis steps
         const uint32_t S = (uint32_t)in.S;
+        uint32_t stride = 1, v0 = (uint32_t)in.vtx_off;
+        uint32_t step[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            v0 += __umul24(I[k], stride);
+            step[k] = I[k] + 1u == S ? stride - __umul24(S, stride) : stride;   // wraps modulo 2^32
+            stride = __umul24(stride, S);
+        }
 #pragma unroll
         for (int c = 0; c < (1 << D); ++c) {
-            uint32_t idx = 0, m = 1;
+            uint32_t v = v0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                uint32_t j = I[k] + ((c >> k) & 1);
-                if (j >= S) j -= S;
-                idx += j * m;
-                m *= S;
-            }
-            vid[c] = in.vtx_off + (int32_t)idx;
+            for (int k = 0; k < D; ++k)
+                if ((c >> k) & 1) v += step[k];
+            vid[c] = v;
+        }
+        // s = 1 and fl(1/s) = 1: f = y - I exactly as (y - I s) * fl(1/s)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            f[k] = __dsub_rn(ax[k].y, (double)I[k]);
+            g[k] = __dsub_rn(1.0, f[k]);
         }
     } else {
+        int lev;
         const uint32_t rank = descend<D>(t, in, I, lds, lds_n, lev);
 #pragma unroll
-        for (int k = 0; k < D; ++k) a[k] = div_pow3(I[k], in.L - lev);
+        for (int c = 0; c < (1 << D); ++c) vid[c] = (uint32_t)t.leaf_vtx[(int64_t)rank * (1 << D) + c];
+        const uint32_t su = pow3_u32(in.L - lev);
+        const double s = (double)su;
+        const double rinv = in.rinv[lev];
 #pragma unroll
-        for (int c = 0; c < (1 << D); ++c) vid[c] = t.leaf_vtx[(int64_t)rank * (1 << D) + c];
-    }
-    const double s = (double)pow3_u32(in.L - lev);
-    const double rinv = in.rinv[lev];
-    double f[D], g[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
-        g[k] = __dsub_rn(1.0, f[k]);
+        for (int k = 0; k < D; ++k) {
+            const uint32_t a = div_pow3(I[k], in.L - lev);
+            f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a * s), rinv);
+            g[k] = __dsub_rn(1.0, f[k]);
+        }
     }
     double w[1 << D];
 #pragma unroll
@@ -226,10 +269,10 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const double *Ej = P.E[j];
-        double e = __dmul_rn(w[0], Ej[vid[0]]);
+        double e = __dmul_rn(w[0], ld_off(Ej, vid[0]));
 #pragma unroll
-        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ej[vid[c]]));
-        if (P.Ep[0]) P.Ep[j][p] = e;
+        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], ld_off(Ej, vid[c])));
+        if (EP && P.Ep[0]) P.Ep[j][p] = e;
         double vj = __dadd_rn(vv[j], __dmul_rn(qmdt, e));
         double xj = __dadd_rn(xv[j], __dmul_rn(vj, dt));
         xj = __dsub_rn(xj, floor(xj));
@@ -238,7 +281,7 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         xv[j] = xj;
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
+    for (int k = 0; k < D; ++k) ax[k] = scale_wrapped(xv[k], in.Sd, bad);
     return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
 }
 
@@ -343,6 +386,7 @@ struct RebinScratch {
     uint32_t *list;       // total runs <= n_tiles * TILE
     uint64_t *scan_state; // per scan block (zeroed per call)
     uint32_t *scan_ctr;   // dynamic block counter (zeroed per call)
+    uint64_t *run_wcnt;   // n_tiles * TILE: fused step, 16-bit count per wavefront
 };
 
 // Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
@@ -578,97 +622,6 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_
     uint32_t n_runs;
     const int cur = tile_sort_emit<IPT, RADIX, false>(S, old_start, tile, cnt, n_bins, sc, status, n_runs);
     for (int i = tid; i < cnt; i += RB_THREADS) sc.perm[lo + i] = S.item[cur][i];
-}
-
-// Fused first pass of a whole step: gather + push of the tile's particles
-// (thread t holds slots t + 256 j), their new bins go straight into the tile
-// sort, and the pushed columns (and the extra columns) are written back in
-// place in the tile's sorted order, staged through LDS one column at a time.
-// The new bins never travel through memory, and the tile sort's LDS work
-// overlaps the memory traffic of the other blocks.
-template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
-__global__ __launch_bounds__(RB_THREADS) void k_push_sort(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
-                                                         double qmdt0, double dt0, const double *qmdt_arr,
-                                                         const double *dt_arr, const int64_t *inst_start,
-                                                         const int64_t *old_start, uint32_t n_bins,
-                                                         RebinScratch sc, Cols extra) {
-    constexpr int TILE = RB_THREADS * IPT;
-    __shared__ TileSmem<IPT, 4, true> S;
-    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
-    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
-    const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
-    const int64_t lo = tile * TILE;
-    const int cnt = (int)min((int64_t)TILE, n - lo);
-    double xv[IPT][D], vv[IPT][D];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const int i = tid + j * RB_THREADS;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            xv[j][k] = i < cnt ? P.x[k][lo + i] : 0.0;
-            vv[j][k] = i < cnt ? P.v[k][lo + i] : 0.0;
-        }
-    }
-    uint32_t bad = 0;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const int i = tid + j * RB_THREADS;
-        if (i < cnt) {
-            const int64_t p = lo + i;
-            int ii = 0;
-            if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
-            const DevInst &in = MULTI ? t.inst[ii] : in0;
-            const double qmdt = (MULTI && qmdt_arr) ? qmdt_arr[ii] : qmdt0;
-            const double dt = (MULTI && dt_arr) ? dt_arr[ii] : dt0;
-            S.key[i] = push_one<D, SCHEME, REG>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
-        }
-    }
-    if (bad) flag_status(t.status, bad);
-    __syncthreads();
-    uint32_t n_runs;
-    const int cur = tile_sort_emit<IPT, 4, true>(S, old_start, tile, cnt, n_bins, sc, t.status, n_runs);
-    // write back in sorted order: one column at a time through the staging area
-    uint64_t *stage = (uint64_t *)S.cnt;
-    uint16_t src[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) src[j] = S.item[cur][tid + j * RB_THREADS];
-    for (int c = 0; c < 2 * D + extra.n; ++c) {
-        const int ce = c - 2 * D;
-        uint64_t ev[IPT];
-        if (c >= 2 * D) {
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const int i = tid + j * RB_THREADS;
-                ev[j] = 0;
-                if (i < cnt)
-                    ev[j] = extra.bytes[ce] == 8 ? ((const uint64_t *)extra.in[ce])[lo + i]
-                                                 : (uint64_t)((const uint32_t *)extra.in[ce])[lo + i];
-            }
-        }
-        __syncthreads();                                  // staging area free (run starts read)
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            uint64_t w;
-            if (c < D) w = __double_as_longlong(xv[j][c]);
-            else if (c < 2 * D) w = __double_as_longlong(vv[j][c - D]);
-            else w = ev[j];
-            stage[tid + j * RB_THREADS] = w;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const int i = tid + j * RB_THREADS;
-            if (i < cnt) {
-                const uint64_t w = stage[src[j]];
-                if (c < D) P.x[c][lo + i] = __longlong_as_double(w);
-                else if (c < 2 * D) P.v[c - D][lo + i] = __longlong_as_double(w);
-                else if (extra.bytes[ce] == 8) ((uint64_t *)extra.in[ce])[lo + i] = w;
-                else ((uint32_t *)extra.in[ce])[lo + i] = (uint32_t)w;
-            }
-        }
-    }
-    (void)n_runs;
 }
 
 // Pass 2: single-pass scan (decoupled look-back) of the per-key (count, runs)
@@ -978,93 +931,311 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_scatter(int64_t n, RebinSc
     }
 }
 
-// Pass 4 of the fused step: the tile is already in sorted order, so slot j of
-// the tile goes to run_dest[run(j)] + (j - run_start): contiguous reads and
-// run-contiguous writes, no staging.
+// ------------------------------------------------------------- fused step
+//
+// A whole step in two passes over the particles.  Both passes push the same
+// tile of particles with the same arithmetic, so they agree on every new bin
+// without the bins ever going through memory.
+//   count: per tile, the number of particles of each key 2*bin + arrived,
+//          split by wavefront (wavefront w owns the tile's slots
+//          [w*64*IPT, (w+1)*64*IPT), in order).  These become the tile's runs.
+//   move:  the runs' destinations are known (scan + placement); each
+//          particle is written to its run's destination plus its rank among
+//          the earlier particles of the tile with the same key.
+// A particle stays iff its slot lies in its new bin's old segment.
+//
+// Keys are gathered per tile in an LDS open-addressing table of 2*TILE
+// slots, so insertion always finds a free slot; every lane inserts and counts
+// its own key (integer atomics, so the counts do not depend on timing).
+
+__device__ __forceinline__ uint32_t key_hash(uint32_t k, int bits) { return (k * 0x9E3779B1u) >> (32 - bits); }
+
+template <int HB>
+__device__ __forceinline__ uint32_t table_insert(uint32_t *keys, uint32_t k) {
+    uint32_t h = key_hash(k, HB);
+    for (;;) {
+        const uint32_t prev = atomicCAS(&keys[h], 0u, k + 1u);
+        if (prev == 0u || prev == k + 1u) return h;
+        h = (h + 1u) & ((1u << HB) - 1u);
+    }
+}
+
+// Slot of key k, or ~0 when absent (at most 2^HB probes).
+template <int HB>
+__device__ __forceinline__ uint32_t table_find(const uint32_t *keys, uint32_t k) {
+    uint32_t h = key_hash(k, HB);
+    for (int i = 0; i < (1 << HB); ++i) {
+        const uint32_t v = keys[h];
+        if (v == k + 1u) return h;
+        if (v == 0u) break;
+        h = (h + 1u) & ((1u << HB) - 1u);
+    }
+    return ~0u;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+constexpr int STEP_RCAP = 256;
+
 template <int IPT>
-__global__ __launch_bounds__(RB_THREADS) void k_scatter_sorted(int64_t n, RebinScratch sc, Cols cols,
-                                                              uint32_t *status) {
-    constexpr int TILE = RB_THREADS * IPT;
-    __shared__ uint16_t s_rstart[TILE + 1];
-    __shared__ uint32_t s_rdest[TILE];
-    const int tid = threadIdx.x;
+struct StepShape {
+    static constexpr int TILE = RB_THREADS * IPT;
+    static constexpr int HB = IPT == 4 ? 11 : (IPT == 8 ? 12 : 13);   // 2*TILE table slots
+    static constexpr int H = 1 << HB;
+    static_assert(H == 2 * TILE, "table size");
+};
+
+// Loads and pushes the tile's particles (slot w*64*IPT + j*64 + lane of
+// thread (w, lane)) and forms their keys; ~0 marks slots past the end.
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__device__ __forceinline__ void step_push_tile(const DevTree &t, const DevInst &in0, const F64Ptrs &P, int64_t n,
+                                               int64_t lo, double qmdt0, double dt0, const double *qa,
+                                               const double *da, const int64_t *inst_start,
+                                               const int64_t *old_start, uint32_t n_bins, const int32_t *lds,
+                                               int lds_n, double (&xv)[IPT][D], double (&vv)[IPT][D],
+                                               uint32_t (&key)[IPT], uint32_t &bad) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    uint32_t nb[IPT];
+    if (!MULTI && lo + RB_THREADS * IPT <= n) {
+        // full tile: no per-slot guards, so the rounds form straight-line code
+        // and their loads (state, field, offsets) overlap
+#pragma unroll
+        for (int j = 0; j < IPT; ++j)
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                xv[j][k] = P.x[k][base + 64 * j];
+                vv[j][k] = P.v[k][base + 64 * j];
+            }
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            uint32_t b = push_one<D, SCHEME, REG, false>(t, in0, P, lds, lds_n, xv[j], vv[j], qmdt0, dt0,
+                                                         base + 64 * j, bad);
+            if (b >= n_bins) bad |= PIC_DEV_RANGE;
+            nb[j] = min(b, n_bins - 1);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int64_t p = base + 64 * j;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                xv[j][k] = p < n ? P.x[k][p] : 0.0;
+                vv[j][k] = p < n ? P.v[k][p] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int64_t p = base + 64 * j;
+            nb[j] = ~0u;
+            if (p < n) {
+                int ii = 0;
+                if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+                const DevInst &in = MULTI ? t.inst[ii] : in0;
+                const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+                const double dt = (MULTI && da) ? da[ii] : dt0;
+                uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
+                if (b >= n_bins) bad |= PIC_DEV_RANGE;
+                nb[j] = min(b, n_bins - 1);
+            }
+        }
+    }
+    // stayer iff the slot lies in its new bin's old segment
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        key[j] = ~0u;
+        if (nb[j] != ~0u) {
+            bool stay = false;
+            if (old_start) {
+                const int64_t s0 = old_start[nb[j]], s1 = old_start[nb[j] + 1];
+                stay = s0 <= p && p < s1;
+            }
+            key[j] = 2u * nb[j] + (stay ? 0u : 1u);
+        }
+    }
+}
+
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_count(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                          double qmdt0, double dt0, const double *qa,
+                                                          const double *da, const int64_t *inst_start,
+                                                          const int64_t *old_start, uint32_t n_bins,
+                                                          RebinScratch sc) {
+    using SS = StepShape<IPT>;
+    __shared__ uint32_t s_key[SS::H];
+    __shared__ uint64_t s_cnt[SS::H];   // 16-bit count per wavefront
+    __shared__ uint32_t s_nruns;
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t lo = tile * SS::TILE;
+    for (int i = tid; i < SS::H; i += RB_THREADS) {
+        s_key[i] = 0u;
+        s_cnt[i] = 0u;
+    }
+    if (tid == 0) s_nruns = 0u;
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    double xv[IPT][D], vv[IPT][D];
+    uint32_t key[IPT];
+    uint32_t bad = 0;
+    step_push_tile<D, SCHEME, REG, MULTI, IPT>(t, in0, P, n, lo, qmdt0, dt0, qa, da, inst_start, old_start, n_bins,
+                                               lds, lds_n, xv, vv, key, bad);
+    if (bad) flag_status(t.status, bad);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        if (key[j] == ~0u) continue;
+        uint32_t slot = table_find<SS::HB>(s_key, key[j]);         // most keys are in already
+        if (slot == ~0u) slot = table_insert<SS::HB>(s_key, key[j]);
+        atomicAdd((unsigned long long *)&s_cnt[slot], 1ull << (16 * w));
+    }
+    __syncthreads();
+    for (int i = tid; i < SS::H; i += RB_THREADS) {
+        const uint32_t k1 = s_key[i];
+        if (!k1) continue;
+        const uint64_t c = s_cnt[i];
+        const uint32_t tot = (uint32_t)((c & 0xffffu) + ((c >> 16) & 0xffffu) + ((c >> 32) & 0xffffu) + (c >> 48));
+        const uint32_t ri = atomicAdd(&s_nruns, 1u);
+        sc.run_key[lo + ri] = k1 - 1u;
+        sc.run_info[lo + ri] = tot << 16;
+        sc.run_wcnt[lo + ri] = c;
+        atomicAdd(&sc.key_cnt[k1 - 1u], tot);
+        atomicAdd(&sc.key_nruns[k1 - 1u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) sc.tile_nruns[tile] = s_nruns;
+}
+
+// Move pass.  Each slot is ranked within its run in tile order (wavefront
+// chunks in order, lanes in order) and written to the run's destination plus
+// that rank.  The tile's run table is loaded together with the particles
+// (its first RB_THREADS entries speculatively: the tile's run area always
+// holds them), so the block waits for memory once and passes one barrier.
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_move(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                         double qmdt0, double dt0, const double *qa,
+                                                         const double *da, const int64_t *inst_start,
+                                                         const int64_t *old_start, uint32_t n_bins,
+                                                         RebinScratch sc, F64Ptrs out, Cols extra) {
+    using SS = StepShape<IPT>;
+    constexpr int TILE = SS::TILE;
+    __shared__ uint32_t s_key[SS::H];
+    __shared__ uint16_t s_run[SS::H];
+    __shared__ uint32_t s_cur[4][TILE];   // per wavefront: next destination of each run
+    __shared__ unsigned long long s_msk[4][STEP_RCAP];
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t tile = blockIdx.x;
     const int64_t lo = tile * TILE;
-    const int cnt = (int)min((int64_t)TILE, n - lo);
-    const uint32_t nr = sc.tile_nruns[tile];
-    const uint32_t ri0 = sc.run_info[lo + tid];
+    for (int i = tid; i < SS::H; i += RB_THREADS) s_key[i] = 0u;
+    for (int i = tid; i < 4 * STEP_RCAP; i += RB_THREADS) (&s_msk[0][0])[i] = 0ull;
+    const uint32_t nr = min(sc.tile_nruns[tile], (uint32_t)TILE);
+    const uint32_t rk0 = sc.run_key[lo + tid];
+    const uint64_t rw0 = sc.run_wcnt[lo + tid];
     const uint32_t rd0 = sc.run_dest[lo + tid];
-    uint64_t val[4][IPT];
-    const int ng = min(cols.n, 4);
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    double xv[IPT][D], vv[IPT][D];
+    uint32_t key[IPT];
+    uint32_t bad = 0;
+    step_push_tile<D, SCHEME, REG, MULTI, IPT>(t, in0, P, n, lo, qmdt0, dt0, qa, da, inst_start, old_start, n_bins,
+                                               lds, lds_n, xv, vv, key, bad);
+    __syncthreads();                          // table cleared (all waves past the clear)
+    for (uint32_t q = tid; q < nr; q += RB_THREADS) {
+        const bool first = q < (uint32_t)RB_THREADS;
+        const uint32_t k = first ? rk0 : sc.run_key[lo + q];
+        const uint64_t c = first ? rw0 : sc.run_wcnt[lo + q];
+        uint32_t d = first ? rd0 : sc.run_dest[lo + q];
+        const uint32_t slot = table_insert<SS::HB>(s_key, k);
+        s_run[slot] = (uint16_t)q;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        if (c >= ng) break;
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const int j = tid + i * RB_THREADS;
-            val[c][i] = 0;
-            if (j < cnt)
-                val[c][i] = cols.bytes[c] == 8 ? ((const uint64_t *)cols.in[c])[lo + j]
-                                               : (uint64_t)((const uint32_t *)cols.in[c])[lo + j];
+        for (int v = 0; v < 4; ++v) {
+            s_cur[v][q] = d;
+            d += (uint32_t)((c >> (16 * v)) & 0xffffu);
         }
     }
-    if ((uint32_t)tid < nr) {
-        s_rstart[tid] = (uint16_t)(ri0 & 0xffffu);
-        s_rdest[tid] = rd0;
-    }
-    for (uint32_t q = tid + RB_THREADS; q < nr; q += RB_THREADS) {
-        s_rstart[q] = (uint16_t)(sc.run_info[lo + q] & 0xffffu);
-        s_rdest[q] = sc.run_dest[lo + q];
-    }
-    if (tid == 0) s_rstart[nr] = (uint16_t)min(cnt, 0xffff);
     __syncthreads();
+    // rank: the lanes of a round that share a run OR their bit into the run's
+    // mask, read it back, and the lowest of them advances the run's cursor;
+    // runs numbered STEP_RCAP and above go through a ballot loop
     uint32_t dst[IPT];
+    uint32_t miss = 0;
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int j = tid + i * RB_THREADS;
-        dst[i] = 0xffffffffu;
-        if (j < cnt) {
-            uint32_t a = 0, b = nr - 1;
-            while (a < b) {
-                const uint32_t m = (a + b + 1) >> 1;
-                if (s_rstart[m] <= j) a = m; else b = m - 1;
+    for (int j = 0; j < IPT; ++j) {
+        const bool valid = key[j] != ~0u;
+        dst[j] = ~0u;
+        uint32_t ri = ~0u;
+        if (valid) {
+            const uint32_t slot = table_find<SS::HB>(s_key, key[j]);
+            if (slot != ~0u) ri = s_run[slot];
+            else miss = 1;
+        }
+        const bool fast = ri < (uint32_t)STEP_RCAP;
+        if (fast) atomicOr(&s_msk[w][ri], 1ull << lane);
+        uint64_t m = 0;
+        uint32_t b = 0;
+        if (fast) {
+            m = s_msk[w][ri];
+            b = s_cur[w][ri];
+        }
+        const uint32_t below = lanes_below(m);
+        if (fast && below == 0) {
+            s_cur[w][ri] = b + (uint32_t)__popcll(m);
+            s_msk[w][ri] = 0ull;
+        }
+        if (fast) dst[j] = b + below;
+        const bool slow = ri != ~0u && !fast;
+        uint64_t todo = __ballot(slow);
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const uint32_t r = (uint32_t)__shfl((int)ri, leader, 64);
+            const uint64_t ms = __ballot(slow && ri == r);
+            todo &= ~ms;
+            uint32_t bs = 0;
+            if (lane == leader) {
+                bs = s_cur[w][r];
+                s_cur[w][r] = bs + (uint32_t)__popcll(ms);
             }
-            dst[i] = s_rdest[a] + (uint32_t)(j - s_rstart[a]);
-            if (dst[i] >= (uint32_t)n) {
-                dst[i] = 0xffffffffu;
-                flag_status(status, PIC_DEV_RANGE);
-            }
+            bs = (uint32_t)__shfl((int)bs, leader, 64);
+            if (slow && ri == r) dst[j] = bs + lanes_below(ms);
+        }
+        if (dst[j] != ~0u && dst[j] >= (uint32_t)n) {   // inconsistent input: never write out of range
+            dst[j] = ~0u;
+            miss = 1;
         }
     }
-    for (int c0 = 0; c0 < cols.n; c0 += 4) {
-        if (c0 > 0) {
+    if (miss) flag_status(t.status, PIC_DEV_RANGE);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c0 + c >= cols.n) break;
+    for (int j = 0; j < IPT; ++j) {
+        if (dst[j] == ~0u) continue;
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int j = tid + i * RB_THREADS;
-                    val[c][i] = 0;
-                    if (j < cnt)
-                        val[c][i] = cols.bytes[c0 + c] == 8 ? ((const uint64_t *)cols.in[c0 + c])[lo + j]
-                                                            : (uint64_t)((const uint32_t *)cols.in[c0 + c])[lo + j];
-                }
-            }
+        for (int k = 0; k < D; ++k) {
+            out.x[k][dst[j]] = xv[j][k];
+            out.v[k][dst[j]] = vv[j][k];
         }
+    }
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    for (int c = 0; c < extra.n; ++c) {
+        if (extra.bytes[c] == 8) {
+            const uint64_t *src = (const uint64_t *)extra.in[c];
+            uint64_t *o = (uint64_t *)extra.out[c];
+            uint64_t v[IPT];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c0 + c >= cols.n) break;
-            if (cols.bytes[c0 + c] == 8) {
-                uint64_t *out = (uint64_t *)cols.out[c0 + c];
+            for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
 #pragma unroll
-                for (int i = 0; i < IPT; ++i)
-                    if (dst[i] != 0xffffffffu) out[dst[i]] = val[c][i];
-            } else {
-                uint32_t *out = (uint32_t *)cols.out[c0 + c];
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u) o[dst[j]] = v[j];
+        } else {
+            const uint32_t *src = (const uint32_t *)extra.in[c];
+            uint32_t *o = (uint32_t *)extra.out[c];
+            uint32_t v[IPT];
 #pragma unroll
-                for (int i = 0; i < IPT; ++i)
-                    if (dst[i] != 0xffffffffu) out[dst[i]] = (uint32_t)val[c][i];
-            }
+            for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u) o[dst[j]] = v[j];
         }
     }
 }
@@ -1116,7 +1287,7 @@ __device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp,
         ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
         const uint32_t I = ax[k].T >> 1;
         a[k] = REG ? I : div_pow3(I, e);
-        f[k] = __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
+        f[k] = REG ? __dsub_rn(ax[k].y, (double)I) : __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
         g[k] = __dsub_rn(1.0, f[k]);
     }
     if (SCHEME == PIC_PIT) {
@@ -1229,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_deposit_vertices(DevTree t, DevInst in0
                     uint32_t cell[D];
 #pragma unroll
                     for (int k = 0; k < D; ++k) cell[k] = ((c >> k) & 1) ? (J[k] == 0 ? S - 1 : J[k] - 1) : J[k];
-                    const int64_t leaf = in.leaf_off + peano_low<D>(cell, in.L);
+                    const int64_t leaf = in.leaf_off + regular_rank<D, REG>(t, in, cell);
                     const double x = partial[leaf * NS + c];
                     sum = first ? x : __dadd_rn(sum, x);
                     first = false;
@@ -1251,7 +1422,7 @@ __global__ __launch_bounds__(256) void k_deposit_vertices(DevTree t, DevInst in0
                         uint32_t Jp = B + half;
                         sh[k] = Jp >= S ? Jp - S : Jp;
                     }
-                    const int64_t bin = in.pidt_off + peano_low<D>(sh, in.L);
+                    const int64_t bin = in.pidt_off + regular_rank<D, REG>(t, in, sh);
                     const double x = partial[bin * NS + sl];
                     sum = first ? x : __dadd_rn(sum, x);
                     first = false;
@@ -1379,7 +1550,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
-        list, scan_state, scan_ctr, total;
+        list, scan_state, scan_ctr, run_wcnt, total;
 };
 
 static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
@@ -1403,6 +1574,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.key_base = o; o = align256(o + keys * 4);
     L.list_off = o; o = align256(o + (keys + 1) * 4);
     L.list = o; o = align256(o + slots * 4);
+    L.run_wcnt = o; o = align256(o + slots * 8);
     L.total = o;
     return L;
 }
@@ -1412,7 +1584,7 @@ Tuning g_tune;
 size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme) {
     // large enough for every supported tile size
     const int64_t nb = n_bins_of(t, scheme);
-    return std::max(rebin_layout(n, nb, 2048).total, rebin_layout(n, nb, 4096).total);
+    return std::max({rebin_layout(n, nb, 1024).total, rebin_layout(n, nb, 2048).total, rebin_layout(n, nb, 4096).total});
 }
 
 template <int IPT>
@@ -1461,6 +1633,7 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.list = (uint32_t *)(base + L.list);
     sc.scan_state = (uint64_t *)(base + L.scan_state);
     sc.scan_ctr = (uint32_t *)(base + L.scan_ctr);
+    sc.run_wcnt = (uint64_t *)(base + L.run_wcnt);
     return sc;
 }
 
@@ -1512,9 +1685,48 @@ hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
                           const double *q, double q_uniform, double *rho, void *scratch, size_t scratch_bytes,
                           hipStream_t s);
 
-#define PIC_DISPATCH_PS(D, SCH, REG, MULTI)                                                                  \
-    PIC_LAUNCH("push_sort", (k_push_sort<D, SCH, REG, MULTI, 8>), dim3(tiles), dim3(RB_THREADS), 0, s, t->dt,     \
-               t->inst0, P, n, qmdt, dt, qa, da, in->inst_start_dev, old_start, (uint32_t)n_bins, sc, extra)
+struct StepArgs {
+    F64Ptrs P, out;
+    int64_t n;
+    double qmdt, dt;
+    const double *qa, *da;
+    const int64_t *inst_start, *old_start;
+    uint32_t n_bins;
+};
+
+template <int D, int SCH, bool REG, bool MULTI, int IPT>
+static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
+                               int64_t *new_start, hipStream_t s) {
+    const int64_t tiles = (a.n + StepShape<IPT>::TILE - 1) / StepShape<IPT>::TILE;
+    if (a.n > 0)
+        PIC_LAUNCH("step_count", (k_step_count<D, SCH, REG, MULTI, IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
+                   t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc);
+    launch_rebin_middle(t, a.n, a.n_bins, StepShape<IPT>::TILE, sc, new_start, s);
+    if (a.n > 0)
+        PIC_LAUNCH("step_move", (k_step_move<D, SCH, REG, MULTI, IPT>), dim3(tiles), dim3(RB_THREADS), 0, s, t->dt,
+                   t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc, a.out,
+                   extra);
+}
+
+template <int D, int SCH, bool REG, bool MULTI>
+static void launch_step_ipt(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
+                            int64_t *new_start, hipStream_t s) {
+    if (g_tune.step_ipt == 4) launch_step_passes<D, SCH, REG, MULTI, 4>(t, a, sc, extra, new_start, s);
+    else launch_step_passes<D, SCH, REG, MULTI, 8>(t, a, sc, extra, new_start, s);
+}
+
+template <int D, int SCH>
+static void launch_step_shape(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
+                              int64_t *new_start, hipStream_t s) {
+    const bool multi = t->n_inst > 1, reg = t->all_regular;
+    if (multi) {
+        if (reg) launch_step_ipt<D, SCH, true, true>(t, a, sc, extra, new_start, s);
+        else launch_step_ipt<D, SCH, false, true>(t, a, sc, extra, new_start, s);
+    } else {
+        if (reg) launch_step_ipt<D, SCH, true, false>(t, a, sc, extra, new_start, s);
+        else launch_step_ipt<D, SCH, false, false>(t, a, sc, extra, new_start, s);
+    }
+}
 
 hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
                        const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,
@@ -1522,53 +1734,31 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
                        void *scratch, size_t scratch_bytes, hipStream_t s) {
     const int64_t n = in->n;
     const int64_t n_bins = n_bins_of(t, scheme);
-    const int tile = RB_THREADS * 8;
+    const int tile = RB_THREADS * g_tune.step_ipt;
     const RebinLayout L = rebin_layout(n, n_bins, tile);
     if (scratch_bytes < L.total || scratch_bytes < deposit_scratch_bytes(t, scheme)) return hipErrorInvalidValue;
     char *base = (char *)scratch;
     const RebinScratch sc = bind_scratch(L, base);
-    const int64_t tiles = (n + tile - 1) / tile;
     const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
-    PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(std::max(zero_words, n_bins), 256, 4096)), dim3(256), 0,
-               s, (uint32_t *)(base + L.key_cnt), zero_words, n > 0 ? old_start : nullptr, n_bins, n, tile, sc);
-    if (n > 0) {
-        F64Ptrs P = make_ptrs(t, in, E, nullptr);
-        const double *qa = pp ? pp->qmdt_dev : nullptr;
-        const double *da = pp ? pp->dt_dev : nullptr;
-        const bool multi = t->n_inst > 1, reg = t->all_regular;
-        if (t->dim == 2) {
-            if (scheme == PIC_PIT) {
-                if (multi) { if (reg) PIC_DISPATCH_PS(2, 0, true, true); else PIC_DISPATCH_PS(2, 0, false, true); }
-                else { if (reg) PIC_DISPATCH_PS(2, 0, true, false); else PIC_DISPATCH_PS(2, 0, false, false); }
-            } else {
-                if (multi) { if (reg) PIC_DISPATCH_PS(2, 1, true, true); else PIC_DISPATCH_PS(2, 1, false, true); }
-                else { if (reg) PIC_DISPATCH_PS(2, 1, true, false); else PIC_DISPATCH_PS(2, 1, false, false); }
-            }
-        } else {
-            if (scheme == PIC_PIT) {
-                if (multi) { if (reg) PIC_DISPATCH_PS(3, 0, true, true); else PIC_DISPATCH_PS(3, 0, false, true); }
-                else { if (reg) PIC_DISPATCH_PS(3, 0, true, false); else PIC_DISPATCH_PS(3, 0, false, false); }
-            } else {
-                if (multi) { if (reg) PIC_DISPATCH_PS(3, 1, true, true); else PIC_DISPATCH_PS(3, 1, false, true); }
-                else { if (reg) PIC_DISPATCH_PS(3, 1, true, false); else PIC_DISPATCH_PS(3, 1, false, false); }
-            }
-        }
-    }
-    launch_rebin_middle(t, n, n_bins, tile, sc, new_start, s);
-    if (n > 0) {
-        Cols cols{};
-        cols.n = 0;
-        for (int k = 0; k < t->dim; ++k) {
-            cols.in[cols.n] = in->x[k]; cols.out[cols.n] = out->x[k]; cols.bytes[cols.n++] = 8;
-        }
-        for (int k = 0; k < t->dim; ++k) {
-            cols.in[cols.n] = in->v[k]; cols.out[cols.n] = out->v[k]; cols.bytes[cols.n++] = 8;
-        }
-        for (int c = 0; c < extra.n; ++c) {
-            cols.in[cols.n] = extra.in[c]; cols.out[cols.n] = extra.out[c]; cols.bytes[cols.n++] = extra.bytes[c];
-        }
-        PIC_LAUNCH("scatter_sorted", k_scatter_sorted<8>, dim3(tiles), dim3(RB_THREADS), 0, s, n, sc, cols,
-                   t->dt.status);
+    PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(zero_words, 256, 4096)), dim3(256), 0, s,
+               (uint32_t *)(base + L.key_cnt), zero_words, nullptr, n_bins, n, tile, sc);
+    StepArgs a;
+    a.P = make_ptrs(t, in, E, nullptr);
+    a.out = make_ptrs(t, out, nullptr, nullptr);
+    a.n = n;
+    a.qmdt = qmdt;
+    a.dt = dt;
+    a.qa = pp ? pp->qmdt_dev : nullptr;
+    a.da = pp ? pp->dt_dev : nullptr;
+    a.inst_start = in->inst_start_dev;
+    a.old_start = old_start;
+    a.n_bins = (uint32_t)n_bins;
+    if (t->dim == 2) {
+        if (scheme == PIC_PIT) launch_step_shape<2, 0>(t, a, sc, extra, new_start, s);
+        else launch_step_shape<2, 1>(t, a, sc, extra, new_start, s);
+    } else {
+        if (scheme == PIC_PIT) launch_step_shape<3, 0>(t, a, sc, extra, new_start, s);
+        else launch_step_shape<3, 1>(t, a, sc, extra, new_start, s);
     }
     const double *q = q_col >= 0 ? (const double *)extra.out[q_col] : nullptr;
     return launch_deposit(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);

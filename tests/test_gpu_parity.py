@@ -312,13 +312,26 @@ def test_fused_step_matches_oracle(name, scheme, kind):
     assert t.status_sync() == 0
 
 
-@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 5 * 2048 + 3])
-def test_fused_and_separate_calls_agree_bitwise(n):
+@pytest.mark.parametrize("spread", [0.05, 0.5])
+@pytest.mark.parametrize("step_tile", [2048, 1024])
+@pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 5 * 2048 + 3])
+def test_fused_and_separate_calls_agree_bitwise(n, step_tile, spread):
+    """spread 0.5 scatters a tile over most of the tree's bins, so tiles hold
+    far more distinct keys than the fast rank path takes."""
     dev = _dev()
+    before = pic.tuning()["step_tile"]
+    pic.tune("step_tile", step_tile)
+    try:
+        _fused_vs_separate(n, dev, spread)
+    finally:
+        pic.tune("step_tile", before)
+
+
+def _fused_vs_separate(n, dev, spread):
     rng = np.random.default_rng(n)
     spec = W.disc_tree(2, 2, 4)
     t = _tree(spec)
-    x, v = rng.random((2, n)), rng.standard_normal((2, n)) * 0.05
+    x, v = rng.random((2, n)), rng.standard_normal((2, n)) * spread
     E = torch.tensor(W.random_field(rng, 2, t.n_vertices, 0.3), device=dev)
     outs = []
     for fused in (False, True):
