@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the spacetree PIC hot path on one MI355X.
 
-One step = pic_gather_push + pic_rebin + pic_deposit over the whole particle
-set, inputs resident in HBM.  Default workload: 2D periodic regular depth-5
-spacetree (243 x 243 leaves), 15,116,544 electrons (256 per cell, Maxwellian
-v_th = 1 cell/step plus 1% beam particles at 8-20 cells/step, 1% density
-perturbation on modes 1..4), PIT, FP64.  The field is the linear-theory
-Langmuir field of the perturbation, fixed over the run (the Poisson solve is
-not part of the step).
+One step = gather + push + rebin + deposit over the whole particle set, inputs
+resident in HBM.  By default the step is the fused entry point pic_step; with
+--path calls it is pic_gather_push + pic_rebin + pic_deposit.
+
+Workloads (--config):
+  2  2D periodic regular depth-5 spacetree (243 x 243 leaves), 15,116,544
+     electrons (256 per cell, Maxwellian v_th = 1 cell/step plus 1% beam
+     particles at 8-20 cells/step, 1% density perturbation on modes 1..4).
+  3  2D adaptive spacetree, depth 4 refined to 6 inside a disc of radius 0.2
+     (74,609 leaves), 9,549,952 electrons (128 per leaf) with per-particle
+     charges, v_th = 1 coarse cell/step.
+The field is fixed over the run (the Poisson solve is not part of the step).
 
 Prints one JSON line (the benchmark contract) with the whole-step throughput,
 a roofline entry for the dominant kernel (algorithmic bytes over its average
-HIP-event duration in the timed region) and the serial FP64 oracle timed on a
-bounded sample on the host as a CPU baseline.
+HIP-event duration in the timed region) and the serial FP64 oracle timed on
+the host as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -38,15 +43,19 @@ def _log(msg):
 
 def algorithmic_bytes(dim: int, per_particle_q: bool):
     """Bytes each kernel must move per particle (FP64 form)."""
-    s_push = 2 * 8 * dim                   # x, v read and written by gather_push
-    s_rec = s_push + (8 if per_particle_q else 0)
-    s_dep = 8 * dim + (8 if per_particle_q else 0)
+    s_push = 2 * 8 * dim                   # x, v
+    q = 8 if per_particle_q else 0
+    s_rec = s_push + q                     # a full record moved by a rebin
+    s_dep = 8 * dim + q                    # positions (and charges) read by the deposit
     return {
-        "gather_push": 2 * s_push + 4,     # + the new bin written
-        "rebin_tiles": 4,                  # bins read
+        "gather_push": 2 * s_push + 4,     # x, v read and written, new bin written
+        "rebin_tiles": 4,                  # new bins read
         "rebin_scatter": 2 * s_rec,        # every record read and written once
         "deposit_bins": s_dep,
-        "step": 2 * s_push + 2 * s_rec + s_dep + 8,
+        "step_count": s_push,              # x, v read
+        "step_move": s_push + s_rec + q,   # x, v (and q) read, the full record written
+        "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
+        "fused": s_push + (s_push + s_rec + q) + s_dep,   # step_count + step_move + deposit_bins
     }
 
 
@@ -65,13 +74,14 @@ def cpu_baseline(wl, scheme, sample, E_np, min_seconds=10.0, max_steps=8):
     o = oracle.OracleTree(wl.tree)
     x = np.ascontiguousarray(wl.x[:, :sample])
     v = np.ascontiguousarray(wl.v[:, :sample])
-    xs, vs, _, start, _ = oracle.initial_sort(o, x, v, None, scheme)
+    q = None if wl.q is None else np.ascontiguousarray(wl.q[:sample])
+    xs, vs, qs, start, _ = oracle.initial_sort(o, x, v, q, scheme)
     steps, spent = 0, 0.0
     while spent < min_seconds and steps < max_steps:
         t0 = time.perf_counter()
-        r = oracle.step(o, xs, vs, E_np, wl.qm * wl.dt, wl.dt, start, scheme, None, wl.q_uniform)
+        r = oracle.step(o, xs, vs, E_np, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
         spent += time.perf_counter() - t0
-        xs, vs, start = r["x"], r["v"], r["bin_start"]
+        xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
         steps += 1
     model = platform.processor() or ""
     try:
@@ -107,15 +117,25 @@ def stored_traffic(kernel: str, workload: str):
     return ent["bytes_per_launch"]
 
 
+WORKLOADS = {
+    2: ("2D periodic regular depth-5 spacetree (243x243 leaves), {n} electrons (256/cell, v_th 1 cell/step, "
+        "1% beam 8-20 cells/step)"),
+    3: ("2D periodic adaptive spacetree, depth 4 refined to 6 in a disc of radius 0.2 ({leaves} leaves), {n} "
+        "electrons (128/leaf, per-particle charge, v_th 1 coarse cell/step)"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, choices=[2, 3], default=2)
     ap.add_argument("--scheme", choices=["pit", "pidt"], default="pit")
-    ap.add_argument("--ppc", type=int, default=256)
+    ap.add_argument("--path", choices=["fused", "calls"], default="fused")
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,33 +156,48 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     scheme = pic.PIT if args.scheme == "pit" else pic.PIDT
-    _log(f"[bench] generating config2 (ppc={args.ppc})")
-    wl = W.config2(ppc=args.ppc)
+    _log(f"[bench] generating config {args.config}")
+    wl = W.config2() if args.config == 2 else W.config3()
     tree = pic.Tree(wl.tree).upload(dev)
     pos = tree.vertex_table().T.astype(np.float64) / wl.tree.finest
     E_np = wl.field(pos)
     E = torch.tensor(E_np, dtype=torch.float64, device=dev)
-    st = pic.Stepper(tree, scheme, wl.x, wl.v, device=dev)
+    st = pic.Stepper(tree, scheme, wl.x, wl.v, q=wl.q, device=dev)
     st.initial_sort()
     torch.cuda.synchronize()
     qmdt, dt = wl.qm * wl.dt, wl.dt
-    _log(f"[bench] n={wl.n} leaves={tree.n_leaves} warmup={args.warmup} steps={args.steps}")
+    step = st.step_fused if args.path == "fused" else st.step
+    _log(f"[bench] n={wl.n} leaves={tree.n_leaves} path={args.path} warmup={args.warmup} steps={args.steps}")
     for _ in range(args.warmup):
-        st.step(E, qmdt, dt, q_uniform=wl.q_uniform)
+        step(E, qmdt, dt, q_uniform=wl.q_uniform)
     torch.cuda.synchronize()
     if tree.status_sync() != 0:
         raise RuntimeError("device status error during warmup")
 
     lib = pic.lib()
+    ab = algorithmic_bytes(wl.dim, wl.q is not None)
+    # per-kernel table from a profiled pass (every launch bracketed by events)
     lib.pic_profile_enable(1)
     kernel_times(lib)                       # drop anything recorded so far
+    for _ in range(args.steps):
+        step(E, qmdt, dt, q_uniform=wl.q_uniform)
+    torch.cuda.synchronize()
+    per_kernel = {}
+    for name, (launches, total) in sorted(kernel_times(lib).items(), key=lambda kv: -kv[1][1]):
+        per_kernel[name] = {"launches": launches, "avg_ms": total / launches}
+    dominant = max((k for k in per_kernel if k in ab), key=lambda k: per_kernel[k]["avg_ms"])
+
+    # timed region: events only around the dominant kernel
+    lib.pic_profile_only(dominant.encode())
+    kernel_times(lib)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st.step(E, qmdt, dt, q_uniform=wl.q_uniform)
+        step(E, qmdt, dt, q_uniform=wl.q_uniform)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = kernel_times(lib)
+    launches, total = kernel_times(lib)[dominant]
+    lib.pic_profile_only(None)
     lib.pic_profile_enable(0)
     if tree.status_sync() != 0:
         raise RuntimeError("device status error in the timed region")
@@ -171,52 +206,51 @@ def main():
     value = wl.n * args.steps / elapsed
     _log(f"[bench] {ms_step:.3f} ms/step, {value:.4g} updates/s")
 
-    ab = algorithmic_bytes(wl.dim, False)
-    per_kernel = {}
-    for name, (launches, total) in sorted(kt.items(), key=lambda kv: -kv[1][1]):
-        per_kernel[name] = {"launches": launches, "avg_ms": total / launches}
-    dominant = max((k for k in per_kernel if k in ab), key=lambda k: per_kernel[k]["avg_ms"])
-    avg_s = per_kernel[dominant]["avg_ms"] * 1e-3
+    ab = algorithmic_bytes(wl.dim, wl.q is not None)
+    avg_s = total / launches * 1e-3
     bytes_launch = ab[dominant] * wl.n
     achieved = bytes_launch / avg_s / 1e9
-    workload = f"config2_{args.scheme}_f64_ppc{args.ppc}"
+    workload = f"config{args.config}_{args.scheme}_f64_{args.path}"
     traffic = stored_traffic(dominant, workload)
+    step_bytes = ab[args.path]
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "bytes_per_launch_algorithmic": bytes_launch,
-                "step_algorithmic_GBps": round(ab["step"] * value / 1e9, 1),
-                "step_frac": round(ab["step"] * value / 1e9 / HBM_PEAK_GBS, 4)}
+                "step_bytes_per_particle": step_bytes,
+                "step_algorithmic_GBps": round(step_bytes * value / 1e9, 1),
+                "step_frac": round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4)}
 
-    # paper's stream benchmark on the same arrays: explicit Euler + reflecting walls, no grid
-    xs = (C.c_void_p * 3)(*[st.x2[k].data_ptr() if k < wl.dim else None for k in range(3)])
-    vs = (C.c_void_p * 3)(*[st.v2[k].data_ptr() if k < wl.dim else None for k in range(3)])
-    st.x2.copy_(st.x)
-    st.v2.copy_(st.v)
-    stream_ptr = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    for _ in range(3):
-        lib.pic_stream_push(wl.dim, wl.n, xs, vs, 1e-3, stream_ptr)
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    for _ in range(args.steps):
-        lib.pic_stream_push(wl.dim, wl.n, xs, vs, 1e-3, stream_ptr)
-    torch.cuda.synchronize()
-    s_el = (time.perf_counter() - s0) / args.steps
-    stream = {"updates_per_s": wl.n / s_el, "GBps": 4 * 8 * wl.dim * wl.n / s_el / 1e9}
+    stream = None
+    if not args.no_stream:
+        # the paper's stream benchmark on the same arrays: explicit Euler + reflecting walls, no grid
+        xs = (C.c_void_p * 3)(*[st.x2[k].data_ptr() if k < wl.dim else None for k in range(3)])
+        vs = (C.c_void_p * 3)(*[st.v2[k].data_ptr() if k < wl.dim else None for k in range(3)])
+        st.x2.copy_(st.x)
+        st.v2.copy_(st.v)
+        stream_ptr = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for _ in range(3):
+            lib.pic_stream_push(wl.dim, wl.n, xs, vs, 1e-3, stream_ptr)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.steps):
+            lib.pic_stream_push(wl.dim, wl.n, xs, vs, 1e-3, stream_ptr)
+        torch.cuda.synchronize()
+        s_el = (time.perf_counter() - s0) / args.steps
+        stream = {"updates_per_s": wl.n / s_el, "GBps": 4 * 8 * wl.dim * wl.n / s_el / 1e9}
 
     cpu = None
     if not args.no_cpu_baseline:
-        _log(f"[bench] cpu baseline on {args.cpu_sample} particles")
+        _log(f"[bench] cpu baseline on up to {args.cpu_sample} particles")
         cpu = cpu_baseline(wl, scheme, min(args.cpu_sample, wl.n), E_np)
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"2D periodic regular depth-5 spacetree (243x243 leaves), {wl.n} electrons "
-                               f"({args.ppc}/cell, v_th 1 cell/step, 1% beam 8-20 cells/step), "
-                               f"{args.scheme.upper()}, FP64",
-                   "particles": wl.n, "leaves": int(tree.n_leaves), "scheme": args.scheme},
+        "config": {"workload": WORKLOADS[args.config].format(n=wl.n, leaves=int(tree.n_leaves)) +
+                               f", {args.scheme.upper()}, FP64, {args.path} path",
+                   "particles": wl.n, "leaves": int(tree.n_leaves), "scheme": args.scheme, "path": args.path},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in per_kernel.items()},

@@ -303,6 +303,13 @@ typedef struct {
 pic_status pic_profile_enable(int32_t on);
 
 /*
+ * Restricts timing to launches of one kernel, named as in pic_kernel_time
+ * (e.g. "step_move"); NULL or "" times every kernel again.  Lets a caller time
+ * one kernel inside a measured region with two events per launch.
+ */
+pic_status pic_profile_only(const char *name);
+
+/*
  * Launch-shape knobs, for the autotuner.  Names and values:
  *   "rebin_tile"    particles per rebin tile, 2048 or 4096 (default 2048);
  *   "rebin_radix"   bits per LDS radix pass of the tile sort, 4 or 5 (default 4);

@@ -17,7 +17,7 @@ EXPORTS = [
     "pic_tree_leaf_table", "pic_tree_vertex_table", "pic_tree_pidt_table", "pic_tree_upload",
     "pic_status_sync", "pic_status_string", "pic_locate", "pic_gather_push", "pic_scratch_bytes",
     "pic_rebin", "pic_deposit", "pic_stream_push", "pic_profile_enable", "pic_profile_read",
-    "pic_tune_set", "pic_tune_get", "pic_step",
+    "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only",
 ]
 
 
@@ -99,6 +99,8 @@ def lib():
         L.pic_stream_push.restype = i32
         L.pic_profile_enable.argtypes = [i32]
         L.pic_profile_enable.restype = i32
+        L.pic_profile_only.argtypes = [C.c_char_p]
+        L.pic_profile_only.restype = i32
         L.pic_profile_read.argtypes = [vp, i32]
         L.pic_profile_read.restype = i32
         L.pic_step.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, dbl, C.POINTER(PushParams), i32,

@@ -20,6 +20,7 @@ struct Rec {
     hipEvent_t a, b;
 };
 bool g_on = false;
+std::string g_only;  // when set, only launches of this kernel name are timed
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -37,6 +38,7 @@ hipEvent_t get_event() {
 
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s), a_(nullptr) {
     if (!g_on) return;
+    if (!g_only.empty() && g_only != name) return;
     a_ = get_event();
     if (a_) hipEventRecord((hipEvent_t)a_, s);
 }
@@ -55,6 +57,11 @@ extern "C" {
 
 pic_status pic_profile_enable(int32_t on) {
     pic::g_on = on != 0;
+    return PIC_OK;
+}
+
+pic_status pic_profile_only(const char *name) {
+    pic::g_only = name ? name : "";
     return PIC_OK;
 }
 
