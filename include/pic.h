@@ -157,10 +157,12 @@ const char *pic_status_string(pic_status s);
 /*
  * One particle set in structure-of-arrays form.  FP64 form: x[k], v[k]
  * (k < dim) are n doubles each, x in [0,1) domain units, v in domain units
- * per unit time.  FP32 form: off[k] in [0,1) is the offset inside the
- * particle's leaf in leaf widths and u[k] the velocity in finest cells per
- * step; the leaf itself is the particle's PIT bin.  Unused pointers may be
- * NULL.
+ * per unit time.  FP32 offset form (trees whose instances are all regular,
+ * with Peano rank tables): off[k] in [0,1) is the offset inside the
+ * particle's finest cell in cell widths and u[k] the velocity in finest cells
+ * per step (v dt 3^L); the cell is implicit in the particle's bin: the leaf
+ * for PIT, and for PIDT the owner vertex J with the cell J - 1 where
+ * off >= 1/2 and J otherwise, per axis.  Unused pointers may be NULL.
  *
  * inst_start_dev: for a forest, n_inst+1 int64 particle offsets: the
  * particles of instance i are [inst_start[i], inst_start[i+1]), in order.
@@ -203,9 +205,14 @@ pic_status pic_locate(const pic_tree *tree, int32_t scheme, int32_t precision,
  *   bin_start_dev  the current segment offsets of p (n_bins+1 int64); needed
  *                by the FP32 form (its cell is implicit in the bin), NULL is
  *                allowed for FP64.
- *   Ep_dev       optional (NULL): dim*n doubles receiving E_p per particle.
+ *   Ep_dev       optional (NULL): dim*n doubles receiving E_p per particle
+ *                (FP64 form only).
  * FP64 arithmetic follows a fixed operation order with no fused multiply-add,
  * so x, v and the bins equal a serial IEEE evaluation of the same formulas.
+ * FP32 form: E is still FP64 at the vertices; weights, gather and push are
+ * FP32, u <- u + fl32(qmdt dt 3^L) E_p, and the cell moves by the integer
+ * floor(off + u) (exact, any distance, periodic) with off keeping the
+ * fraction.  PIC_E_ARG for FP32 on trees without the tables.
  */
 pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precision,
                            pic_particles *p, const double *const *E_dev,
@@ -214,7 +221,9 @@ pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precisi
                            void *stream);
 
 /*
- * Scratch bytes needed by pic_rebin / pic_deposit for n particles.
+ * Scratch bytes needed by pic_rebin / pic_deposit / pic_step for n particles
+ * (the FP32 form of pic_step also keeps the new bins there).  0 for invalid
+ * arguments.
  */
 size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_t precision);
 
@@ -243,7 +252,8 @@ pic_status pic_rebin(const pic_tree *tree, int32_t scheme, int64_t n,
  * (bin_start_dev from pic_rebin for the same scheme).  rho_dev receives
  * n_vertices doubles (vertex charge, overwritten).  q_dev: per-particle
  * charge (n doubles) or NULL for q_uniform.  No floating-point atomics: each
- * vertex sums its contributions in a fixed order.
+ * vertex sums its contributions in a fixed order.  FP32 form: per bin, FP32
+ * compensated (Kahan) sums, then FP64 over lanes and incident bins.
  */
 pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
                        const pic_particles *p, const int64_t *bin_start_dev,
@@ -252,14 +262,14 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
 
 /*
  * One whole step in a single call: the same result as pic_gather_push, then
- * pic_rebin (in -> out) and pic_deposit (on out), with fused kernels (paper
- * Sec. 2 items 1, 3, 4; Sec. 4 re-binning).  The first kernel pushes a tile
- * of particles, sorts it by new bin in LDS and writes it back in place in
- * tile-sorted order, so the new bins never go through memory; the second
- * moves each run of equal bin to its destination.
- *   in                 sorted set with offsets bin_start_dev; its x, v and
- *                      extra columns are used as workspace and hold no
- *                      meaningful data afterwards.
+ * pic_rebin (in -> out) and pic_deposit (on out) (paper Sec. 2 items 1, 3, 4;
+ * Sec. 4 re-binning).  FP64 form: two passes over `in`, which stays
+ * unchanged: the first pushes each tile of particles and counts its particles
+ * per (new bin, arrived); after a scan over the counts the second pushes the
+ * tile again (same arithmetic, same bins) and writes every particle straight
+ * to its final slot.  FP32 form: gather + push in place on `in` (whose
+ * off/u then hold the pushed values in the old order), then the re-bin.
+ *   in                 sorted set with offsets bin_start_dev.
  *   extra_in/out       n_extra further columns (4 or 8 bytes) carried along.
  *   q_column           index of the per-particle charge among the extra
  *                      columns (8-byte), or -1 to use q_uniform.
@@ -273,6 +283,23 @@ pic_status pic_step(const pic_tree *tree, int32_t scheme, int32_t precision, pic
                     void *const *extra_out_dev, const int32_t *extra_bytes, int32_t q_column, double q_uniform,
                     pic_particles *out, int64_t *new_bin_start_dev, double *rho_dev, void *scratch_dev,
                     size_t scratch_bytes, void *stream);
+
+/*
+ * Convert a particle set between the FP64 form and the FP32 offset form
+ * (trees whose instances are all regular with Peano rank tables).  p must
+ * carry both x, v and off, u.  dt: the step the FP32 velocity is scaled by
+ * (u = v dt 3^L), or per instance through params->dt_dev.
+ *   to_precision PIC_F32_OFFSET: from x, v (any order) writes off = fl32(x 3^L
+ *                - I), u = fl32(v dt 3^L) and, in bin_dev, each particle's bin
+ *                in the FP32 form (rounding can carry a particle to the next
+ *                cell, so re-bin before stepping: pic_rebin with the old
+ *                offsets keeps all others in place).
+ *   to_precision PIC_F64: from off, u of a sorted set (bin_start_dev) writes
+ *                x = (cell + off) / 3^L, v = u / (dt 3^L).
+ */
+pic_status pic_convert(const pic_tree *tree, int32_t scheme, int32_t to_precision, pic_particles *p, double dt,
+                       const pic_push_params *params, const int64_t *bin_start_dev, uint32_t *bin_dev,
+                       void *stream);
 
 /* ------------------------------------------------------- measurement aids */
 
@@ -318,7 +345,11 @@ pic_status pic_profile_only(const char *name);
  *   "scatter_nt"    1 = non-temporal stores for the re-binned records (default 0);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
- *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048).
+ *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048);
+ *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
+ *                   regular instances (up to 2^21 cells per level), which the
+ *                   arithmetic kernels and the FP32 form use; 0 = none, every
+ *                   tree takes the descent kernels (default 1).
  * Every setting gives the same results; pic_scratch_bytes covers all of them.
  * Affects calls enqueued afterwards.  Unknown names or values: PIC_E_ARG
  * (pic_tune_get returns -1).

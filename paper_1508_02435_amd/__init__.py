@@ -19,7 +19,7 @@ from . import _capi
 from ._capi import F32_OFFSET, F64, PIDT, PIT, PicError, check, lib
 
 __all__ = ["Tree", "PIT", "PIDT", "F64", "F32_OFFSET", "PicError", "locate", "gather_push", "rebin",
-           "deposit", "scratch_bytes", "Stepper", "lib", "tune", "tuning", "TUNING_KNOBS", "step"]
+           "deposit", "scratch_bytes", "Stepper", "Stepper32", "lib", "tune", "tuning", "TUNING_KNOBS", "step"]
 
 
 def _ptr(t) -> Optional[int]:
@@ -159,7 +159,7 @@ def _check_inst(tree, inst_start):
 
 
 TUNING_KNOBS = {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1), "scatter_nt": (0, 1),
-                "scatter_group": (1, 2, 4), "deposit_lanes": (16, 32, 64), "step_tile": (2048, 1024)}
+                "scatter_group": (1, 2, 4), "deposit_lanes": (16, 32, 64), "step_tile": (2048, 1024), "regular_tables": (1, 0)}
 
 
 def tune(name: str, value: int):
@@ -373,4 +373,135 @@ class Stepper:
         step(self.tree, self.scheme, self.x, self.v, E, qmdt, dt, self.start, self.x2, self.v2, self.start2,
              self.rho, self.scratch, extra_in, extra_out, q_col, q_uniform, inst_start=self.inst_start,
              qmdt_dev=qmdt_dev, dt_dev=dt_dev)
+        self._swap()
+
+
+class Stepper32:
+    """Device state of one particle set in the FP32 offset form.
+
+    ``off`` (dim, n) float32 offsets inside the finest cell, ``u`` (dim, n)
+    float32 velocities in finest cells per step; the cell is implicit in the
+    bin.  Built from an FP64 set (any order) for a step ``dt`` (or per
+    instance ``dt_dev``), sorted once, then stepped with the three calls or
+    the single fused call.  Trees whose instances are all regular only.
+    """
+
+    def __init__(self, tree: Tree, scheme: int, x, v, dt: float = 0.0, q=None, ids=None, inst_start=None,
+                 dt_dev=None, device="cuda"):
+        import torch
+        self.tree, self.scheme = tree, scheme
+        self.n = int(x.shape[1])
+        self.dt, self.dt_dev = float(dt), dt_dev
+        dev = torch.device(device)
+        d = tree.dim
+        self.off = torch.empty((d, self.n), dtype=torch.float32, device=dev)
+        self.u = torch.empty_like(self.off)
+        self.off2 = torch.empty_like(self.off)
+        self.u2 = torch.empty_like(self.off)
+        self.q = None if q is None else torch.as_tensor(np.ascontiguousarray(q), dtype=torch.float64,
+                                                        device=dev).contiguous()
+        self.ids = None if ids is None else torch.as_tensor(np.ascontiguousarray(ids), device=dev).contiguous()
+        self.q2 = None if self.q is None else torch.empty_like(self.q)
+        self.ids2 = None if self.ids is None else torch.empty_like(self.ids)
+        self.bin = torch.empty(self.n, dtype=torch.int32, device=dev)
+        nb = tree.n_bins(scheme)
+        self.start = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.start2 = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        sb = scratch_bytes(tree, self.n, scheme, F32_OFFSET)
+        _need(sb > 0, "the FP32 form needs a tree whose instances are all regular (with Peano tables)")
+        self.scratch = torch.empty(sb // 8 + 1, dtype=torch.int64, device=dev)
+        self.rho = torch.zeros(tree.n_vertices, dtype=torch.float64, device=dev)
+        self.inst_start = inst_start
+        _check_inst(tree, inst_start)
+        xd = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
+        vd = torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev).contiguous()
+        self._convert(F32_OFFSET, xd, vd, None)
+        self._rebin(None)
+
+    def _pp(self, qmdt_dev=None, dt_dev=None):
+        return _capi.PushParams(_ptr(qmdt_dev), _ptr(dt_dev if dt_dev is not None else self.dt_dev))
+
+    def _convert(self, to, xd, vd, bin_start):
+        P = _particles(self.n, x=xd, v=vd, off=self.off, u=self.u, inst_start=self.inst_start)
+        pp = self._pp()
+        check(lib().pic_convert(self.tree.handle, self.scheme, to, C.byref(P), self.dt, C.byref(pp),
+                                C.c_void_p(_ptr(bin_start)) if bin_start is not None else None,
+                                C.c_void_p(_ptr(self.bin)), C.c_void_p(_stream(None))), "pic_convert")
+
+    def _cols(self):
+        d = self.tree.dim
+        ins = [self.off[k] for k in range(d)] + [self.u[k] for k in range(d)]
+        outs = [self.off2[k] for k in range(d)] + [self.u2[k] for k in range(d)]
+        for a, b in ((self.q, self.q2), (self.ids, self.ids2)):
+            if a is not None:
+                ins.append(a); outs.append(b)
+        return ins, outs
+
+    def _swap(self):
+        self.off, self.off2 = self.off2, self.off
+        self.u, self.u2 = self.u2, self.u
+        self.q, self.q2 = self.q2, self.q
+        self.ids, self.ids2 = self.ids2, self.ids
+        self.start, self.start2 = self.start2, self.start
+
+    def _rebin(self, old_start):
+        ins, outs = self._cols()
+        rebin(self.tree, self.scheme, self.bin, old_start, ins, outs, self.start2, self.scratch)
+        self._swap()
+
+    def to_f64(self):
+        """(x, v) FP64 device tensors of the current (sorted) set."""
+        import torch
+        xd = torch.empty((self.tree.dim, self.n), dtype=torch.float64, device=self.off.device)
+        vd = torch.empty_like(xd)
+        self._convert(F64, xd, vd, self.start)
+        return xd, vd
+
+    def step(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+        """Three separate calls: gather_push (in place), rebin, deposit."""
+        for k in range(self.tree.dim):
+            _check_vec(E[k], self.tree.n_vertices, f"E[{k}]")
+        P = _particles(self.n, off=self.off, u=self.u, inst_start=self.inst_start)
+        Eptr = (C.c_void_p * 3)(*[_ptr(E[k]) if k < self.tree.dim else None for k in range(3)])
+        pp = self._pp(qmdt_dev, dt_dev)
+        check(lib().pic_gather_push(self.tree.handle, self.scheme, F32_OFFSET, C.byref(P), Eptr, float(qmdt),
+                                    float(dt), C.byref(pp), C.c_void_p(_ptr(self.start)),
+                                    C.c_void_p(_ptr(self.bin)), None, C.c_void_p(_stream(None))),
+              "pic_gather_push")
+        self._rebin(self.start)
+        self.deposit(q_uniform)
+
+    def deposit(self, q_uniform=0.0):
+        P = _particles(self.n, off=self.off, u=self.u, inst_start=self.inst_start)
+        check(lib().pic_deposit(self.tree.handle, self.scheme, F32_OFFSET, C.byref(P),
+                                C.c_void_p(_ptr(self.start)),
+                                C.c_void_p(_ptr(self.q)) if self.q is not None else None, float(q_uniform),
+                                C.c_void_p(_ptr(self.rho)), C.c_void_p(_ptr(self.scratch)),
+                                self.scratch.numel() * self.scratch.element_size(), C.c_void_p(_stream(None))),
+              "pic_deposit")
+
+    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+        """The same step through the single call pic_step (FP32 form)."""
+        for k in range(self.tree.dim):
+            _check_vec(E[k], self.tree.n_vertices, f"E[{k}]")
+        P = _particles(self.n, off=self.off, u=self.u, inst_start=self.inst_start)
+        Q = _particles(self.n, off=self.off2, u=self.u2, inst_start=self.inst_start)
+        Eptr = (C.c_void_p * 3)(*[_ptr(E[k]) if k < self.tree.dim else None for k in range(3)])
+        pp = self._pp(qmdt_dev, dt_dev)
+        extra_in, extra_out, q_col = [], [], -1
+        if self.q is not None:
+            q_col = 0
+            extra_in.append(self.q); extra_out.append(self.q2)
+        if self.ids is not None:
+            extra_in.append(self.ids); extra_out.append(self.ids2)
+        ne = len(extra_in)
+        ins = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_in])
+        outs = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_out])
+        sizes = (C.c_int32 * max(ne, 1))(*[c.element_size() for c in extra_in])
+        check(lib().pic_step(self.tree.handle, self.scheme, F32_OFFSET, C.byref(P), C.c_void_p(_ptr(self.start)),
+                             Eptr, float(qmdt), float(dt), C.byref(pp), ne, ins, outs, sizes, q_col,
+                             float(q_uniform), C.byref(Q), C.c_void_p(_ptr(self.start2)),
+                             C.c_void_p(_ptr(self.rho)), C.c_void_p(_ptr(self.scratch)),
+                             self.scratch.numel() * self.scratch.element_size(), C.c_void_p(_stream(None))),
+              "pic_step")
         self._swap()

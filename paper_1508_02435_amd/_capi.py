@@ -17,7 +17,7 @@ EXPORTS = [
     "pic_tree_leaf_table", "pic_tree_vertex_table", "pic_tree_pidt_table", "pic_tree_upload",
     "pic_status_sync", "pic_status_string", "pic_locate", "pic_gather_push", "pic_scratch_bytes",
     "pic_rebin", "pic_deposit", "pic_stream_push", "pic_profile_enable", "pic_profile_read",
-    "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only",
+    "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only", "pic_convert",
 ]
 
 
@@ -106,6 +106,8 @@ def lib():
         L.pic_step.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, dbl, C.POINTER(PushParams), i32,
                                vp, vp, vp, i32, dbl, C.POINTER(Particles), vp, vp, vp, sz, vp]
         L.pic_step.restype = i32
+        L.pic_convert.argtypes = [vp, i32, i32, C.POINTER(Particles), dbl, C.POINTER(PushParams), vp, vp, vp]
+        L.pic_convert.restype = i32
         L.pic_tune_set.argtypes = [C.c_char_p, i64]
         L.pic_tune_set.restype = i32
         L.pic_tune_get.argtypes = [C.c_char_p]

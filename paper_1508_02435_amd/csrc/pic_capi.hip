@@ -79,7 +79,7 @@ pic_status assemble(pic_tree *t) {
     std::vector<uint32_t> ptab;
     for (int i = 0; i < ni; ++i) {
         const HostInst &h = t->inst[i];
-        if (!h.regular || tab_off[h.L] >= 0) continue;
+        if (!g_tune.regular_tables || !h.regular || tab_off[h.L] >= 0) continue;
         int64_t cells = 1;
         for (int k = 0; k < dim; ++k) cells *= (int64_t)h.S;
         if (cells > kMaxTab) continue;
@@ -91,6 +91,13 @@ pic_status assemble(pic_tree *t) {
             uint32_t a[3] = {(uint32_t)(c % S), (uint32_t)((c / S) % S), (uint32_t)(c / ((int64_t)S * S))};
             dst[c] = dim == 2 ? peano_low<2>(a, h.L) : peano_low<3>(a, h.L);
         }
+    }
+    std::vector<uint32_t> ctab(ptab.size());
+    for (int l = 0; l <= PIC_MAX_LEVEL; ++l) {
+        if (tab_off[l] < 0) continue;
+        int64_t cells = 1;
+        for (int k = 0; k < dim; ++k) cells *= (int64_t)pow3_u64(l);
+        for (int64_t c = 0; c < cells; ++c) ctab[tab_off[l] + ptab[tab_off[l] + c]] = (uint32_t)c;
     }
 
     size_t o = 0;
@@ -111,6 +118,7 @@ pic_status assemble(pic_tree *t) {
     t->o_vpptr = o; o = align256(o + (size_t)(NV + 1) * 4);
     t->o_vpinc = o; o = align256(o + (size_t)vpinc.size() * 4);
     t->o_ptab = o; o = align256(o + ptab.size() * 4);
+    t->o_ctab = o; o = align256(o + ctab.size() * 4);
     t->device_bytes = (int64_t)o;
     t->image.assign(o, 0);
 
@@ -165,6 +173,7 @@ pic_status assemble(pic_tree *t) {
     put(t->image, t->o_vpptr, vpptr.data(), NV + 1);
     put(t->image, t->o_vpinc, vpinc.data(), (int64_t)vpinc.size());
     put(t->image, t->o_ptab, ptab.data(), (int64_t)ptab.size());
+    put(t->image, t->o_ctab, ctab.data(), (int64_t)ctab.size());
     t->reg_kernels = 1;
     for (int i = 0; i < ni; ++i) t->reg_kernels &= di[i].regular && di[i].ptab >= 0;
     t->inst0 = di[0];
@@ -198,7 +207,13 @@ void bind(pic_tree *t) {
     d.vpinc_ptr = (const int32_t *)(b + t->o_vpptr);
     d.vpinc = (const int32_t *)(b + t->o_vpinc);
     d.peano_tab = (const uint32_t *)(b + t->o_ptab);
+    d.cell_tab = (const uint32_t *)(b + t->o_ctab);
     d.status = (uint32_t *)(b + t->o_status);
+}
+
+// The FP32 form needs every instance regular with a Peano rank table.
+bool valid_precision(const pic_tree *t, int precision) {
+    return precision == PIC_F64 || (precision == PIC_F32_OFFSET && t->reg_kernels);
 }
 
 bool particles_ok(const pic_tree *t, const pic_particles *p, int precision, bool need_v) {
@@ -389,21 +404,24 @@ pic_status pic_locate(const pic_tree *t, int32_t scheme, int32_t precision, cons
 pic_status pic_gather_push(const pic_tree *t, int32_t scheme, int32_t precision, pic_particles *p,
                            const double *const *E, double qmdt, double dt, const pic_push_params *params,
                            const int64_t *bin_start, uint32_t *bin, double *Ep, void *stream) {
-    if (!t || !valid_scheme(scheme) || precision != PIC_F64 || !particles_ok(t, p, precision, true))
+    if (!t || !valid_scheme(scheme) || !valid_precision(t, precision) || !particles_ok(t, p, precision, true))
         return PIC_E_ARG;
     if (p->n > 0 && (!E || !bin)) return PIC_E_ARG;
     if (p->n > 0)
         for (int k = 0; k < t->dim; ++k)
             if (!E[k]) return PIC_E_ARG;
+    if (precision == PIC_F32_OFFSET && ((p->n > 0 && !bin_start) || Ep)) return PIC_E_ARG;
     if (!t->dev) return PIC_E_STATE;
-    (void)bin_start;
-    return launch_gather_push(t, scheme, p, E, qmdt, dt, params, bin, Ep, (hipStream_t)stream) == hipSuccess
-               ? PIC_OK : PIC_E_HIP;
+    hipError_t e = precision == PIC_F64
+                       ? launch_gather_push(t, scheme, p, E, qmdt, dt, params, bin, Ep, (hipStream_t)stream)
+                       : launch_gather_push_f32(t, scheme, p, E, qmdt, dt, params, bin_start, nullptr, 0, bin,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
 size_t pic_scratch_bytes(const pic_tree *t, int64_t n, int32_t scheme, int32_t precision) {
-    if (!t || !valid_scheme(scheme) || n < 0) return 0;
-    (void)precision;
+    if (!t || !valid_scheme(scheme) || n < 0 || !valid_precision(t, precision)) return 0;
+    if (precision == PIC_F32_OFFSET) return step_f32_scratch_bytes(t, n, scheme);
     return std::max(rebin_scratch_bytes(t, n, scheme), deposit_scratch_bytes(t, scheme));
 }
 
@@ -433,13 +451,17 @@ pic_status pic_rebin(const pic_tree *t, int32_t scheme, int64_t n, const uint32_
 pic_status pic_deposit(const pic_tree *t, int32_t scheme, int32_t precision, const pic_particles *p,
                        const int64_t *bin_start, const double *q, double q_uniform, double *rho, void *scratch,
                        size_t scratch_bytes, void *stream) {
-    if (!t || !valid_scheme(scheme) || precision != PIC_F64 || !particles_ok(t, p, precision, false))
+    if (!t || !valid_scheme(scheme) || !valid_precision(t, precision) || !particles_ok(t, p, precision, false))
         return PIC_E_ARG;
     if (!bin_start || !rho || !scratch) return PIC_E_ARG;
     if (scratch_bytes < deposit_scratch_bytes(t, scheme)) return PIC_E_SCRATCH;
     if (!t->dev) return PIC_E_STATE;
-    return launch_deposit(t, scheme, p, bin_start, q, q_uniform, rho, scratch, scratch_bytes,
-                          (hipStream_t)stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+    hipError_t e = precision == PIC_F64
+                       ? launch_deposit(t, scheme, p, bin_start, q, q_uniform, rho, scratch, scratch_bytes,
+                                        (hipStream_t)stream)
+                       : launch_deposit_f32(t, scheme, p, bin_start, q, q_uniform, rho, scratch, scratch_bytes,
+                                            (hipStream_t)stream);
+    return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
 pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_particles *in,
@@ -447,13 +469,18 @@ pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_pa
                     const pic_push_params *params, int32_t n_extra, void *const *extra_in, void *const *extra_out,
                     const int32_t *extra_bytes, int32_t q_column, double q_uniform, pic_particles *out,
                     int64_t *new_bin_start, double *rho, void *scratch, size_t scratch_bytes, void *stream) {
-    if (!t || !valid_scheme(scheme) || precision != PIC_F64 || !particles_ok(t, in, precision, true) || !out)
+    if (!t || !valid_scheme(scheme) || !valid_precision(t, precision) || !particles_ok(t, in, precision, true) ||
+        !out)
         return PIC_E_ARG;
     if (out->n != in->n || !particles_ok(t, out, precision, true)) return PIC_E_ARG;
     if (in->n > 0 && (!E || !bin_start)) return PIC_E_ARG;
     if (in->n > 0)
-        for (int k = 0; k < t->dim; ++k)
-            if (!E[k] || in->x[k] == out->x[k] || in->v[k] == out->v[k]) return PIC_E_ARG;
+        for (int k = 0; k < t->dim; ++k) {
+            if (!E[k]) return PIC_E_ARG;
+            if (precision == PIC_F64 && (in->x[k] == out->x[k] || in->v[k] == out->v[k])) return PIC_E_ARG;
+            if (precision == PIC_F32_OFFSET && (in->off[k] == out->off[k] || in->u[k] == out->u[k]))
+                return PIC_E_ARG;
+        }
     if (!new_bin_start || !rho || !scratch) return PIC_E_ARG;
     if (n_extra < 0 || n_extra > 16 - 2 * t->dim) return PIC_E_ARG;
     if (n_extra > 0 && (!extra_in || !extra_out || !extra_bytes)) return PIC_E_ARG;
@@ -470,8 +497,26 @@ pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_pa
     if (q_column >= 0 && extra_bytes[q_column] != 8) return PIC_E_ARG;
     if (scratch_bytes < pic_scratch_bytes(t, in->n, scheme, precision)) return PIC_E_SCRATCH;
     if (!t->dev) return PIC_E_STATE;
-    return launch_step(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start, q_column, q_uniform,
-                       rho, scratch, scratch_bytes, (hipStream_t)stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+    hipError_t e = precision == PIC_F64
+                       ? launch_step(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start,
+                                     q_column, q_uniform, rho, scratch, scratch_bytes, (hipStream_t)stream)
+                       : launch_step_f32(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start,
+                                         q_column, q_uniform, rho, scratch, scratch_bytes, (hipStream_t)stream);
+    return e == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+pic_status pic_convert(const pic_tree *t, int32_t scheme, int32_t to_precision, pic_particles *p, double dt,
+                       const pic_push_params *params, const int64_t *bin_start, uint32_t *bin, void *stream) {
+    if (!t || !valid_scheme(scheme) || !t->reg_kernels) return PIC_E_ARG;
+    if (to_precision != PIC_F64 && to_precision != PIC_F32_OFFSET) return PIC_E_ARG;
+    if (!particles_ok(t, p, PIC_F64, true) || !particles_ok(t, p, PIC_F32_OFFSET, true)) return PIC_E_ARG;
+    if (p->n > 0 && to_precision == PIC_F32_OFFSET && !bin) return PIC_E_ARG;
+    if (p->n > 0 && to_precision == PIC_F64 && !bin_start) return PIC_E_ARG;
+    const bool per_inst = params && params->dt_dev;
+    if (!per_inst && !(dt > 0.0)) return PIC_E_ARG;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_convert(t, scheme, to_precision, p, dt, params, bin_start, bin, (hipStream_t)stream) == hipSuccess
+               ? PIC_OK : PIC_E_HIP;
 }
 
 pic_status pic_tune_set(const char *name, int64_t value) {
@@ -492,6 +537,9 @@ pic_status pic_tune_set(const char *name, int64_t value) {
     } else if (k == "deposit_lanes") {
         if (value != 16 && value != 32 && value != 64) return PIC_E_ARG;
         g_tune.deposit_lanes = (int)value;
+    } else if (k == "regular_tables") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.regular_tables = (int)value;
     } else if (k == "step_tile") {
         if (value != 1024 && value != 2048) return PIC_E_ARG;
         g_tune.step_ipt = (int)(value / 256);
@@ -514,6 +562,7 @@ int64_t pic_tune_get(const char *name) {
     if (k == "scatter_group") return g_tune.scatter_group;
     if (k == "deposit_lanes") return g_tune.deposit_lanes;
     if (k == "step_tile") return 256 * (int64_t)g_tune.step_ipt;
+    if (k == "regular_tables") return g_tune.regular_tables;
     return -1;
 }
 

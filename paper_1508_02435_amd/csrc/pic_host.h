@@ -50,7 +50,7 @@ struct pic_tree {
     // byte offsets of the tables inside the image
     int64_t o_status = 0, o_inst = 0, o_node = 0, o_ubase = 0, o_umeta = 0, o_llev = 0, o_lvtx = 0,
             o_lpidt = 0, o_plev = 0, o_linst = 0, o_pinst = 0, o_vinst = 0, o_vptr = 0, o_vinc = 0,
-            o_vpptr = 0, o_vpinc = 0, o_ptab = 0;
+            o_vpptr = 0, o_vpinc = 0, o_ptab = 0, o_ctab = 0;
     int64_t n_nodes = 0, n_vinc = 0, n_vpinc = 0;
     void *dev = nullptr;               // bound device buffer (caller-owned)
     pic::DevTree dt{};                 // device view, valid once uploaded
@@ -104,6 +104,7 @@ struct Tuning {
     int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
     int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
     int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
+    int regular_tables = 1; // build Peano rank tables for regular instances of trees created afterwards
 };
 extern Tuning g_tune;
 hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
@@ -115,6 +116,19 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
                        const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,
                        pic_particles *out, int64_t *new_start, int q_col, double q_uniform, double *rho,
                        void *scratch, size_t scratch_bytes, hipStream_t s);
+hipError_t launch_gather_push_f32(const pic_tree *t, int scheme, pic_particles *p, const double *const *E,
+                                  double qmdt, double dt, const pic_push_params *pp, const int64_t *bin_start,
+                                  const uint32_t *tile_bin, int tile, uint32_t *bin, hipStream_t s);
+hipError_t launch_deposit_f32(const pic_tree *t, int scheme, const pic_particles *p, const int64_t *bin_start,
+                              const double *q, double q_uniform, double *rho, void *scratch, size_t scratch_bytes,
+                              hipStream_t s);
+hipError_t launch_convert(const pic_tree *t, int scheme, int to_precision, pic_particles *p, double dt,
+                          const pic_push_params *pp, const int64_t *bin_start, uint32_t *bin, hipStream_t s);
+size_t step_f32_scratch_bytes(const pic_tree *t, int64_t n, int scheme);
+hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
+                           const double *const *E, double qmdt, double dt, const pic_push_params *pp,
+                           const Cols &extra, pic_particles *out, int64_t *new_start, int q_col, double q_uniform,
+                           double *rho, void *scratch, size_t scratch_bytes, hipStream_t s);
 hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *const *v, double dt, hipStream_t s);
 
 }  // namespace pic

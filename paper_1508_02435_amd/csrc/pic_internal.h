@@ -120,6 +120,7 @@ struct DevTree {
     const int32_t *vpinc_ptr;   // n_vtx + 1: CSR vertex -> (pidt bin * 3^d + stencil slot), ascending
     const int32_t *vpinc;
     const uint32_t *peano_tab;  // per level of regular instances: Peano rank of finest cell c0 + S c1 (+ S^2 c2)
+    const uint32_t *cell_tab;   // the inverse: lattice index c0 + S c1 (+ S^2 c2) of each Peano rank
     uint32_t *status;           // sticky device status word
 };
 

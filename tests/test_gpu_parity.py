@@ -343,3 +343,36 @@ def _fused_vs_separate(n, dev, spread):
         outs.append([a.cpu().numpy().copy() for a in (st.x, st.v, st.ids, st.start, st.rho)])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,scheme", [("config1", 0), ("config1", 1), ("small_3d", 0), ("small_3d", 1)])
+def test_regular_tree_without_tables_matches_oracle(name, scheme):
+    """Regular trees too large for Peano tables take the descent kernels;
+    tables switched off exercise that path on small trees."""
+    dev = _dev()
+    wl = W.by_name(name)
+    before = pic.tuning()["regular_tables"]
+    pic.tune("regular_tables", 0)
+    try:
+        t = _tree(wl.tree)
+    finally:
+        pic.tune("regular_tables", before)
+    assert pic.scratch_bytes(t, wl.n, scheme, pic.F32_OFFSET) == 0      # no tables: no FP32 form either
+    o = oracle.OracleTree(wl.tree)
+    rng = np.random.default_rng(21)
+    st = pic.Stepper(t, scheme, wl.x, wl.v, ids=np.arange(wl.n), device=dev)
+    st.initial_sort()
+    xs, vs, qs, start, perm = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+    ids = perm
+    for it in range(2):
+        E = _field(o, wl, rng, "random")
+        st.step_fused(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+        r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+        torch.cuda.synchronize()
+        ids = ids[r["perm"]]
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+        assert np.array_equal(st.ids.cpu().numpy(), ids)
+        assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
+    assert t.status_sync() == 0

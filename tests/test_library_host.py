@@ -153,3 +153,43 @@ def test_tuning_knobs_accept_only_listed_values():
     finally:
         for k, v in before.items():
             pic.tune(k, v)
+
+
+def test_fp32_form_needs_regular_trees_with_tables():
+    L = _capi.lib()
+    adaptive = pic.Tree(W.disc_tree(2, 2, 4))
+    regular = pic.Tree(W.regular_tree(2, 3))
+    assert pic.scratch_bytes(adaptive, 1000, pic.PIT, pic.F32_OFFSET) == 0
+    assert pic.scratch_bytes(regular, 1000, pic.PIT, pic.F32_OFFSET) > pic.scratch_bytes(regular, 1000, pic.PIT)
+    P = _capi.Particles()
+    P.n = 10
+    P.off[0], P.off[1], P.u[0], P.u[1] = 0x1000, 0x2000, 0x3000, 0x4000
+    E = (C.c_void_p * 3)(0x5000, 0x6000, None)
+    nb = C.c_void_p(0x7000)
+    start = C.c_void_p(0x8000)
+    assert L.pic_gather_push(adaptive.handle, 0, 1, C.byref(P), E, 0.0, 0.0, None, start, nb, None, None) \
+        == _capi.PIC_E_ARG
+    # FP32 needs the segment offsets (its cell is implicit in the bin) and produces no E_p
+    assert L.pic_gather_push(regular.handle, 0, 1, C.byref(P), E, 0.0, 0.0, None, None, nb, None, None) \
+        == _capi.PIC_E_ARG
+    assert L.pic_gather_push(regular.handle, 0, 1, C.byref(P), E, 0.0, 0.0, None, start, nb,
+                             C.c_void_p(0x9000), None) == _capi.PIC_E_ARG
+    assert L.pic_gather_push(regular.handle, 0, 1, C.byref(P), E, 0.0, 0.0, None, start, nb, None, None) \
+        == _capi.PIC_E_STATE                                   # arguments fine, nothing uploaded
+    # conversion needs both forms' pointers and a positive dt
+    assert L.pic_convert(regular.handle, 0, 1, C.byref(P), 0.5, None, None, nb, None) == _capi.PIC_E_ARG
+    P.x[0], P.x[1], P.v[0], P.v[1] = 0xa000, 0xb000, 0xc000, 0xd000
+    assert L.pic_convert(regular.handle, 0, 1, C.byref(P), 0.0, None, None, nb, None) == _capi.PIC_E_ARG
+    assert L.pic_convert(regular.handle, 0, 1, C.byref(P), 0.5, None, None, nb, None) == _capi.PIC_E_STATE
+    assert L.pic_convert(adaptive.handle, 0, 1, C.byref(P), 0.5, None, None, nb, None) == _capi.PIC_E_ARG
+
+
+def test_tables_off_gives_no_fp32_form():
+    before = pic.tuning()["regular_tables"]
+    pic.tune("regular_tables", 0)
+    try:
+        t = pic.Tree(W.regular_tree(2, 3))
+    finally:
+        pic.tune("regular_tables", before)
+    assert pic.scratch_bytes(t, 1000, pic.PIT, pic.F32_OFFSET) == 0
+    assert pic.scratch_bytes(t, 1000, pic.PIT) > 0
