@@ -41,6 +41,22 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def algorithmic_bytes_f32(dim: int, per_particle_q: bool):
+    """Bytes each kernel must move per particle (FP32 offset form)."""
+    s_push = 2 * 4 * dim                   # off, u
+    q = 8 if per_particle_q else 0
+    s_rec = s_push + q
+    s_dep = 4 * dim + q
+    return {
+        "gather_push_f32": 2 * s_push + 4,
+        "rebin_tiles": 4,
+        "rebin_scatter": 2 * s_rec,
+        "deposit_bins_f32": s_dep,
+        "fused": 2 * s_push + 2 * s_rec + s_dep + 8,
+        "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
+    }
+
+
 def algorithmic_bytes(dim: int, per_particle_q: bool):
     """Bytes each kernel must move per particle (FP64 form)."""
     s_push = 2 * 8 * dim                   # x, v
@@ -122,7 +138,39 @@ WORKLOADS = {
         "1% beam 8-20 cells/step)"),
     3: ("2D periodic adaptive spacetree, depth 4 refined to 6 in a disc of radius 0.2 ({leaves} leaves), {n} "
         "electrons (128/leaf, per-particle charge, v_th 1 coarse cell/step)"),
+    4: ("3D periodic regular depth-4 spacetree (81^3 leaves), {n} electrons (64/cell, v_th 1 cell/step, "
+        "5% isotropic 1-10 cells/step)"),
 }
+
+
+def fp32_accuracy(pic, torch, tree, scheme, wl, E, dev):
+    """One step of the FP32 form against the FP64 form (which equals the
+    serial oracle bit for bit) from the same sorted state, error per quantity."""
+    import numpy as np
+    s64 = pic.Stepper(tree, scheme, wl.x, wl.v, q=wl.q, ids=np.arange(wl.n), device=dev)
+    s64.initial_sort()
+    s32 = pic.Stepper32(tree, scheme, s64.x, s64.v, dt=wl.dt, q=s64.q, ids=s64.ids, device=dev)
+    S = float(3 ** wl.tree.max_level)
+    s64.step_fused(E, wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+    s32.step_fused(E, wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+    x32, v32 = s32.to_f64()
+    torch.cuda.synchronize()
+    inv = torch.empty_like(s64.ids)
+    inv[s64.ids] = torch.arange(wl.n, device=dev, dtype=s64.ids.dtype)
+    j = inv[s32.ids]
+    dx = (x32 - s64.x[:, j]).abs()
+    dx = torch.minimum(dx, 1.0 - dx) * S
+    b32 = torch.repeat_interleave(torch.arange(len(s32.start) - 1, device=dev), s32.start.diff())
+    b64 = torch.repeat_interleave(torch.arange(len(s64.start) - 1, device=dev), s64.start.diff())
+    moved = (b32 != b64[j]).sum().item()
+    out = {"position_max_abs_cells": dx.max().item(),
+           "velocity_max_rel": ((v32 - s64.v[:, j]).abs().max() / s64.v.abs().max()).item(),
+           "rho_max_rel_normwise": ((s32.rho - s64.rho).abs().max() / s64.rho.abs().max()).item(),
+           "bins_differing_fraction": moved / wl.n,
+           "reference": "FP64 form of the same step (bit-exact to the serial oracle in the parity tests)"}
+    del s64, s32
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -130,7 +178,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, choices=[2, 3], default=2)
+    ap.add_argument("--config", type=int, choices=[2, 3, 4], default=2)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--scheme", choices=["pit", "pidt"], default="pit")
     ap.add_argument("--path", choices=["fused", "calls"], default="fused")
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
@@ -157,13 +206,18 @@ def main():
     dev = torch.device("cuda:0")
     scheme = pic.PIT if args.scheme == "pit" else pic.PIDT
     _log(f"[bench] generating config {args.config}")
-    wl = W.config2() if args.config == 2 else W.config3()
+    wl = {2: W.config2, 3: W.config3, 4: W.config4}[args.config]()
     tree = pic.Tree(wl.tree).upload(dev)
     pos = tree.vertex_table().T.astype(np.float64) / wl.tree.finest
     E_np = wl.field(pos)
     E = torch.tensor(E_np, dtype=torch.float64, device=dev)
-    st = pic.Stepper(tree, scheme, wl.x, wl.v, q=wl.q, device=dev)
-    st.initial_sort()
+    f32 = args.precision == "f32"
+    accuracy = fp32_accuracy(pic, torch, tree, scheme, wl, E, dev) if f32 else None
+    if f32:
+        st = pic.Stepper32(tree, scheme, wl.x, wl.v, dt=wl.dt, q=wl.q, device=dev)
+    else:
+        st = pic.Stepper(tree, scheme, wl.x, wl.v, q=wl.q, device=dev)
+        st.initial_sort()
     torch.cuda.synchronize()
     qmdt, dt = wl.qm * wl.dt, wl.dt
     step = st.step_fused if args.path == "fused" else st.step
@@ -175,7 +229,7 @@ def main():
         raise RuntimeError("device status error during warmup")
 
     lib = pic.lib()
-    ab = algorithmic_bytes(wl.dim, wl.q is not None)
+    ab = (algorithmic_bytes_f32 if f32 else algorithmic_bytes)(wl.dim, wl.q is not None)
     # per-kernel table from a profiled pass (every launch bracketed by events)
     lib.pic_profile_enable(1)
     kernel_times(lib)                       # drop anything recorded so far
@@ -206,11 +260,10 @@ def main():
     value = wl.n * args.steps / elapsed
     _log(f"[bench] {ms_step:.3f} ms/step, {value:.4g} updates/s")
 
-    ab = algorithmic_bytes(wl.dim, wl.q is not None)
     avg_s = total / launches * 1e-3
     bytes_launch = ab[dominant] * wl.n
     achieved = bytes_launch / avg_s / 1e9
-    workload = f"config{args.config}_{args.scheme}_f64_{args.path}"
+    workload = f"config{args.config}_{args.scheme}_{args.precision}_{args.path}"
     traffic = stored_traffic(dominant, workload)
     step_bytes = ab[args.path]
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -222,7 +275,7 @@ def main():
                 "step_frac": round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4)}
 
     stream = None
-    if not args.no_stream:
+    if not args.no_stream and not f32:
         # the paper's stream benchmark on the same arrays: explicit Euler + reflecting walls, no grid
         xs = (C.c_void_p * 3)(*[st.x2[k].data_ptr() if k < wl.dim else None for k in range(3)])
         vs = (C.c_void_p * 3)(*[st.v2[k].data_ptr() if k < wl.dim else None for k in range(3)])
@@ -240,22 +293,24 @@ def main():
         stream = {"updates_per_s": wl.n / s_el, "GBps": 4 * 8 * wl.dim * wl.n / s_el / 1e9}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not f32:
         _log(f"[bench] cpu baseline on up to {args.cpu_sample} particles")
         cpu = cpu_baseline(wl, scheme, min(args.cpu_sample, wl.n), E_np)
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config].format(n=wl.n, leaves=int(tree.n_leaves)) +
-                               f", {args.scheme.upper()}, FP64, {args.path} path",
+                               f", {args.scheme.upper()}, {'FP32 offsets' if f32 else 'FP64'}, {args.path} path",
                    "particles": wl.n, "leaves": int(tree.n_leaves), "scheme": args.scheme, "path": args.path},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in per_kernel.items()},
         "stream_benchmark": stream,
     }
+    if accuracy is not None:
+        out["fp32_vs_fp64"] = accuracy
     print(json.dumps(out), flush=True)
 
 

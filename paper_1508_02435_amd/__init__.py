@@ -153,6 +153,16 @@ def _particles(n, x=None, v=None, off=None, u=None, inst_start=None) -> _capi.Pa
     return P
 
 
+def _to_dev(a, dtype, dev):
+    """A contiguous device copy of a NumPy array or tensor (None stays None)."""
+    import torch
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=dev, dtype=dtype if dtype is not None else a.dtype, copy=True).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev).contiguous()
+
+
 def _check_inst(tree, inst_start):
     if tree.n_inst > 1:
         _check_vec(inst_start, tree.n_inst + 1, "inst_start")
@@ -299,11 +309,10 @@ class Stepper:
         self.tree, self.scheme = tree, scheme
         self.n = int(x.shape[1])
         dev = torch.device(device)
-        self.x = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
-        self.v = torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev).contiguous()
-        self.q = None if q is None else torch.as_tensor(np.ascontiguousarray(q), dtype=torch.float64,
-                                                        device=dev).contiguous()
-        self.ids = None if ids is None else torch.as_tensor(np.ascontiguousarray(ids), device=dev).contiguous()
+        self.x = _to_dev(x, torch.float64, dev)
+        self.v = _to_dev(v, torch.float64, dev)
+        self.q = _to_dev(q, torch.float64, dev)
+        self.ids = _to_dev(ids, None, dev)
         self.x2 = torch.empty_like(self.x)
         self.v2 = torch.empty_like(self.v)
         self.q2 = None if self.q is None else torch.empty_like(self.q)
@@ -398,9 +407,8 @@ class Stepper32:
         self.u = torch.empty_like(self.off)
         self.off2 = torch.empty_like(self.off)
         self.u2 = torch.empty_like(self.off)
-        self.q = None if q is None else torch.as_tensor(np.ascontiguousarray(q), dtype=torch.float64,
-                                                        device=dev).contiguous()
-        self.ids = None if ids is None else torch.as_tensor(np.ascontiguousarray(ids), device=dev).contiguous()
+        self.q = _to_dev(q, torch.float64, dev)
+        self.ids = _to_dev(ids, None, dev)
         self.q2 = None if self.q is None else torch.empty_like(self.q)
         self.ids2 = None if self.ids is None else torch.empty_like(self.ids)
         self.bin = torch.empty(self.n, dtype=torch.int32, device=dev)
@@ -413,8 +421,8 @@ class Stepper32:
         self.rho = torch.zeros(tree.n_vertices, dtype=torch.float64, device=dev)
         self.inst_start = inst_start
         _check_inst(tree, inst_start)
-        xd = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
-        vd = torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev).contiguous()
+        xd = _to_dev(x, torch.float64, dev)
+        vd = _to_dev(v, torch.float64, dev)
         self._convert(F32_OFFSET, xd, vd, None)
         self._rebin(None)
 
