@@ -173,12 +173,124 @@ def fp32_accuracy(pic, torch, tree, scheme, wl, E, dev):
     return out
 
 
+def run_batched(args, scheme):
+    """Config 5: 64 independent 2D Langmuir instances (depths 3-5, 0.1M-4M
+    particles each) as one forest, one launch sequence per step, autotuned
+    and replayed from a HIP graph; FP64 and FP32, against the same 64
+    instances stepped one after another as plain single trees (FP64)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_1508_02435_amd as pic
+    from paper_1508_02435_amd import autotune
+
+    dev = torch.device("cuda:0")
+    _log("[bench] generating config 5")
+    insts = W.config5()
+    n = sum(w.n for w in insts)
+    t = pic.Tree([w.tree for w in insts]).upload(dev)
+    inst_start = torch.tensor(np.concatenate([[0], np.cumsum([w.n for w in insts])]), dtype=torch.int64, device=dev)
+    Es = [w.field(pic.Tree(w.tree).vertex_table().T.astype(np.float64) / w.tree.finest) for w in insts]
+    E = torch.tensor(np.concatenate(Es, axis=1), dtype=torch.float64, device=dev)
+    qd = torch.tensor([w.qm * w.dt for w in insts], dtype=torch.float64, device=dev)
+    dd = torch.tensor([w.dt for w in insts], dtype=torch.float64, device=dev)
+    q_uniform = -1.0 / n
+    kw = dict(q_uniform=q_uniform, qmdt_dev=qd, dt_dev=dd)
+    steps = max(2, args.steps - args.steps % 2)
+    lib = pic.lib()
+    results = {}
+
+    def timed_graph(st, label):
+        knobs = autotune.autotune(st, E, 0.0, 0.0, fused=True, steps=2, **kw)
+        g = pic.StepGraph(st, E, 0.0, 0.0, **kw)
+        for _ in range(max(1, args.warmup // 2)):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // 2):
+            g.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if t.status_sync() != 0:
+            raise RuntimeError(f"device status error in the {label} run")
+        results[label] = {"updates_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps, "knobs": knobs}
+        _log(f"[bench] {label}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.4g} updates/s, knobs {knobs}")
+
+    _log(f"[bench] forest: {len(insts)} instances, {n} particles")
+    x = np.concatenate([w.x for w in insts], axis=1)
+    v = np.concatenate([w.v for w in insts], axis=1)
+    st = pic.Stepper(t, scheme, x, v, inst_start=inst_start, device=dev)
+    st.initial_sort()
+    timed_graph(st, "batched_f64")
+    # per-kernel table and roofline of the batched FP64 step (profiled eager steps)
+    lib.pic_profile_enable(1)
+    kernel_times(lib)
+    for _ in range(steps):
+        st.step_fused(E, 0.0, 0.0, **kw)
+    torch.cuda.synchronize()
+    kt = kernel_times(lib)
+    lib.pic_profile_enable(0)
+    per_kernel = {k: {"launches": a, "avg_ms": tot / a} for k, (a, tot) in kt.items()}
+    ab = algorithmic_bytes(2, False)
+    dominant = max((k for k in per_kernel if k in ab), key=lambda k: per_kernel[k]["avg_ms"])
+    achieved = ab[dominant] * n / (per_kernel[dominant]["avg_ms"] * 1e-3) / 1e9
+    del st
+    torch.cuda.empty_cache()
+
+    st = pic.Stepper32(t, scheme, x, v, inst_start=inst_start, dt_dev=dd, device=dev)
+    timed_graph(st, "batched_f32")
+    del st
+    torch.cuda.empty_cache()
+
+    # the same instances as 64 plain single-tree FP64 runs, one after another
+    plain = []
+    for w in insts:
+        ti = pic.Tree(w.tree).upload(dev)
+        si = pic.Stepper(ti, scheme, w.x, w.v, device=dev)
+        si.initial_sort()
+        Ei = torch.tensor(w.field(ti.vertex_table().T.astype(np.float64) / w.tree.finest), device=dev)
+        plain.append((ti, si, Ei, w))
+    for _ in range(args.warmup):
+        for ti, si, Ei, w in plain:
+            si.step_fused(Ei, w.qm * w.dt, w.dt, q_uniform=q_uniform)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for ti, si, Ei, w in plain:
+            si.step_fused(Ei, w.qm * w.dt, w.dt, q_uniform=q_uniform)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    results["plain_f64"] = {"updates_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps}
+    _log(f"[bench] plain_f64: {1e3 * el / steps:.3f} ms/step")
+    del plain
+    torch.cuda.empty_cache()
+
+    b = results["batched_f64"]
+    out = {
+        "metric": METRIC, "value": b["updates_per_s"], "unit": "particle updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"64 independent 2D Langmuir instances (regular depths 3-5, 0.1M-4M electrons "
+                               f"each, {n} in total) as one forest, {args.scheme.upper()}, FP64, fused step "
+                               f"replayed from a HIP graph, autotuned launch shape",
+                   "particles": n, "instances": len(insts), "scheme": args.scheme, "path": "fused"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "step_algorithmic_GBps": round(ab["fused"] * b["updates_per_s"] / 1e9, 1),
+                     "step_frac": round(ab["fused"] * b["updates_per_s"] / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": None,
+        "kernels_ms": {k: round(vv["avg_ms"], 4) for k, vv in sorted(per_kernel.items(), key=lambda kv: -kv[1]["avg_ms"])},
+        "batched": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, choices=[2, 3, 4], default=2)
+    ap.add_argument("--config", type=int, choices=[2, 3, 4, 5], default=2)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--scheme", choices=["pit", "pidt"], default="pit")
     ap.add_argument("--path", choices=["fused", "calls"], default="fused")
@@ -205,6 +317,8 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     scheme = pic.PIT if args.scheme == "pit" else pic.PIDT
+    if args.config == 5:
+        return run_batched(args, scheme)
     _log(f"[bench] generating config {args.config}")
     wl = {2: W.config2, 3: W.config3, 4: W.config4}[args.config]()
     tree = pic.Tree(wl.tree).upload(dev)

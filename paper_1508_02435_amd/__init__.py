@@ -513,3 +513,36 @@ class Stepper32:
                              self.scratch.numel() * self.scratch.element_size(), C.c_void_p(_stream(None))),
               "pic_step")
         self._swap()
+
+
+class StepGraph:
+    """Two consecutive steps of a stepper captured in one HIP graph.
+
+    Every launch of a step goes to the current stream and nothing in it
+    allocates, synchronises or writes through memset nodes (counters are
+    cleared by kernels), so the step sequence can be captured and replayed.
+    Two steps are captured so that the double buffers return to their places;
+    each replay advances the state by two steps.  The field, the step
+    parameters and all buffers are fixed at capture.
+    """
+
+    def __init__(self, stepper, E, qmdt, dt, q_uniform=0.0, fused=True, **kw):
+        import torch
+        self.stepper = stepper
+        f = stepper.step_fused if fused else stepper.step
+        args = (E, qmdt, dt)
+        kw = dict(kw, q_uniform=q_uniform)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):              # warm-up outside the capture
+            f(*args, **kw)
+            f(*args, **kw)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            f(*args, **kw)
+            f(*args, **kw)
+
+    def replay(self):
+        self.graph.replay()
