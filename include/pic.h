@@ -346,6 +346,14 @@ pic_status pic_profile_only(const char *name);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
  *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048);
+ *   "step_rank"     pic_step's passes: 1 = the first pass ranks every particle inside
+ *                   its tile and the second only pushes and writes, 0 = the first
+ *                   pass only counts and the second ranks (default 1);
+ *   "xcd_tiles"     1 = pic_step's tiles are dealt to the chip's 8 XCDs in contiguous
+ *                   chunks, 0 = in block order (default 1);
+ *   "emit_stage"    1 = the writing pass of pic_step stages each column through LDS
+ *                   in tile-sorted order, 0 = it stores straight from registers
+ *                   (default 1);
  *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
  *                   regular instances (up to 2^21 cells per level), which the
  *                   arithmetic kernels and the FP32 form use; 0 = none, every

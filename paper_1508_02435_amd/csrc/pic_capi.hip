@@ -546,6 +546,15 @@ pic_status pic_tune_set(const char *name, int64_t value) {
     } else if (k == "scatter_nt") {
         if (value != 0 && value != 1) return PIC_E_ARG;
         g_tune.scatter_nt = (int)value;
+    } else if (k == "step_rank") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.step_rank = (int)value;
+    } else if (k == "xcd_tiles") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.xcd_tiles = (int)value;
+    } else if (k == "emit_stage") {
+        if (value != 0 && value != 1) return PIC_E_ARG;
+        g_tune.emit_stage = (int)value;
     } else {
         return PIC_E_ARG;
     }
@@ -563,6 +572,9 @@ int64_t pic_tune_get(const char *name) {
     if (k == "deposit_lanes") return g_tune.deposit_lanes;
     if (k == "step_tile") return 256 * (int64_t)g_tune.step_ipt;
     if (k == "regular_tables") return g_tune.regular_tables;
+    if (k == "step_rank") return g_tune.step_rank;
+    if (k == "xcd_tiles") return g_tune.xcd_tiles;
+    if (k == "emit_stage") return g_tune.emit_stage;
     return -1;
 }
 

@@ -199,9 +199,9 @@ struct F64Ptrs {
 //   E_j = w_0 E_j[v_0] + w_1 E_j[v_1] + ...  in corner order,
 //   v_j = v_j + qmdt E_j,  x_j = x_j + v_j dt,  x_j = x_j - floor(x_j), 1 -> 0.
 // push_one updates xv, vv in place, stores E_p when P.Ep[0] is set, and
-// returns the particle's new bin; non-finite or out-of-box input sets bits
-// in `bad`.
-template <int D, int SCHEME, bool REG, bool EP = true>
+// returns the particle's new bin (0 without KEY); non-finite or out-of-box
+// input sets bits in `bad`.
+template <int D, int SCHEME, bool REG, bool EP = true, bool KEY = true>
 __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in, const F64Ptrs &P,
                                              const int32_t *lds, int lds_n, double (&xv)[D], double (&vv)[D],
                                              double qmdt, double dt, int64_t p, uint32_t &bad) {
@@ -280,6 +280,7 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         vv[j] = vj;
         xv[j] = xj;
     }
+    if (!KEY) return 0u;
 #pragma unroll
     for (int k = 0; k < D; ++k) ax[k] = scale_wrapped(xv[k], in.Sd, bad);
     return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
@@ -387,6 +388,7 @@ struct RebinScratch {
     uint64_t *scan_state; // per scan block (zeroed per call)
     uint32_t *scan_ctr;   // dynamic block counter (zeroed per call)
     uint64_t *run_wcnt;   // n_tiles * TILE: fused step, 16-bit count per wavefront
+    uint32_t *meta;       // n_tiles * TILE: fused step, run index | rank << 16 per particle
 };
 
 // Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
@@ -1240,6 +1242,287 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_move(DevTree t, DevInst in0
     }
 }
 
+// ------------------------------------------------------ fused step, ranked
+//
+// The same two passes, with the ranking moved into the first one.
+//   rank:  per tile, each particle's key 2*bin + arrived and its rank among
+//          the tile's particles with that key (tile order), stored as one
+//          word per particle: run index | rank << 16.  The tile's runs (key,
+//          count) go to the run table as before.
+//   emit:  push again (no bin), destination = run destination + rank.  No
+//          LDS and no barrier for regular trees.
+// Both passes push with the same arithmetic, so the emitted state is the
+// state the rank pass binned.
+//
+// Ranking inside a round (64 lanes, one slot each) without ordering
+// assumptions on LDS atomics: every lane writes its lane id to a per-wave tag
+// of its table slot and reads the tag back, which gives all lanes of a slot
+// the same representative lane; each lane then ORs its bit into the mask of
+// that representative and reads the mask, whose lanes below its own give its
+// rank.  The lowest lane of a mask advances the wave's count of the slot.
+// The representative a tag ends up with depends on timing, the masks do not.
+
+template <int IPT>
+struct RankShape {
+    static constexpr int TILE = RB_THREADS * IPT;
+    static constexpr int HB = IPT == 4 ? 10 : (IPT == 8 ? 11 : 12);   // TILE table slots
+    static constexpr int H = 1 << HB;
+    static_assert(H == TILE, "table size");
+};
+
+// Block b's tile when the tiles are spread over the chip's 8 XCDs in
+// contiguous chunks (consecutive blocks go to consecutive XCDs), so that the
+// tiles an XCD runs at the same time are neighbours and share its L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int on) {
+    if (!on) return b;
+    const int64_t x = b & 7, k = b >> 3, q = tiles >> 3, r = tiles & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                         double qmdt0, double dt0, const double *qa,
+                                                         const double *da, const int64_t *inst_start,
+                                                         const int64_t *old_start, uint32_t n_bins,
+                                                         RebinScratch sc, uint32_t *meta, int xcd) {
+    using RS = RankShape<IPT>;
+    __shared__ uint32_t s_key[RS::H];            // key + 1 (0: empty); run index after compaction
+    __shared__ uint16_t s_wc[4][RS::H];          // per wavefront count of each slot, then its offset
+    __shared__ uint8_t s_tag[4][RS::H];          // per wavefront representative lane of each slot
+    __shared__ unsigned long long s_msk[4][64];  // per wavefront lane mask of each representative
+    __shared__ uint32_t s_wsum[4];
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tiles = gridDim.x;
+    const int64_t tile = xcd_tile(blockIdx.x, tiles, xcd);
+    const int64_t lo = tile * RS::TILE;
+    for (int i = tid; i < RS::H; i += RB_THREADS) {
+        s_key[i] = 0u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_wc[v][i] = 0;
+    }
+    s_msk[w][lane] = 0ull;
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    double xv[IPT][D], vv[IPT][D];
+    uint32_t key[IPT];
+    uint32_t bad = 0;
+    step_push_tile<D, SCHEME, REG, MULTI, IPT>(t, in0, P, n, lo, qmdt0, dt0, qa, da, inst_start, old_start, n_bins,
+                                               lds, lds_n, xv, vv, key, bad);
+    if (bad) flag_status(t.status, bad);
+    __syncthreads();   // table cleared
+    uint32_t slot[IPT], rk[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        slot[j] = 0u;
+        if (key[j] != ~0u) {
+            slot[j] = table_find<RS::HB>(s_key, key[j]);
+            if (slot[j] == ~0u) slot[j] = table_insert<RS::HB>(s_key, key[j]);
+        }
+    }
+    volatile uint8_t *tag = s_tag[w];
+    volatile unsigned long long *msk = s_msk[w];
+    volatile uint16_t *wc = s_wc[w];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        rk[j] = 0u;
+        if (key[j] == ~0u) continue;
+        tag[slot[j]] = (uint8_t)lane;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t rep = tag[slot[j]];
+        atomicOr((unsigned long long *)&msk[rep], 1ull << lane);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t m = msk[rep];
+        const uint32_t base = wc[slot[j]];
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t below = lanes_below(m);
+        if (below == 0u) {
+            wc[slot[j]] = (uint16_t)(base + (uint32_t)__popcll(m));
+            msk[rep] = 0ull;
+        }
+        __builtin_amdgcn_wave_barrier();
+        rk[j] = base + below;
+    }
+    __syncthreads();
+    // compaction in slot order (a block scan): run index and tile-local
+    // start of every occupied slot; the per-wave counts become per-wave
+    // offsets (counts of the earlier wavefronts)
+    uint32_t k1[IPT], tot[IPT], packed = 0;
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int i = tid * IPT + e;
+        k1[e] = s_key[i];
+        tot[e] = 0;
+        if (k1[e]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t c = s_wc[v][i];
+                s_wc[v][i] = (uint16_t)tot[e];
+                tot[e] += c;
+            }
+            packed += 1u + (tot[e] << 16);
+        }
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(packed, s_wsum, &total);
+    uint32_t ri = ex & 0xffffu, lb = ex >> 16;
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        if (!k1[e]) continue;
+        sc.run_key[lo + ri] = k1[e] - 1u;
+        sc.run_info[lo + ri] = lb | (tot[e] << 16);
+        atomicAdd(&sc.key_cnt[k1[e] - 1u], tot[e]);
+        atomicAdd(&sc.key_nruns[k1[e] - 1u], 1u);
+        s_key[tid * IPT + e] = ri;
+        ++ri;
+        lb += tot[e];
+    }
+    __syncthreads();
+    if (tid == 0) sc.tile_nruns[tile] = total & 0xffffu;
+    const int64_t pbase = lo + (int64_t)w * 64 * IPT + lane;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        if (key[j] == ~0u) continue;
+        meta[pbase + 64 * j] = s_key[slot[j]] | ((s_wc[w][slot[j]] + rk[j]) << 16);
+    }
+}
+
+// Emit pass: slot p of tile T writes its pushed state to
+// run_dest[T's run area + rid] + rank.  With STAGE the tile's records are
+// first put in tile-local sorted order (runs one after the other, each run at
+// its start from the run table) through LDS, one column at a time, so that a
+// wavefront's stores cover consecutive destinations of a few runs instead of
+// a few elements of each of many runs.
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT, bool STAGE>
+__global__ __launch_bounds__(RB_THREADS) void k_step_emit(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                         double qmdt0, double dt0, const double *qa,
+                                                         const double *da, const int64_t *inst_start,
+                                                         const uint32_t *meta, const uint32_t *run_dest,
+                                                         const uint32_t *run_info, F64Ptrs out, Cols extra,
+                                                         int xcd) {
+    constexpr int TILE = RB_THREADS * IPT;
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    __shared__ uint64_t s_val[STAGE ? TILE : 1];
+    __shared__ uint32_t s_dst[STAGE ? TILE : 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+    if (STAGE)
+        for (int i = tid; i < TILE; i += RB_THREADS) s_dst[i] = ~0u;
+    double xv[IPT][D], vv[IPT][D];
+    uint32_t mt[IPT], dst[IPT], q[IPT];
+    uint32_t bad = 0;
+    const bool full = lo + TILE <= n;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        const bool ok = full || p < n;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xv[j][k] = ok ? P.x[k][p] : 0.0;
+            vv[j][k] = ok ? P.v[k][p] : 0.0;
+        }
+        mt[j] = ok ? meta[p] : 0u;
+    }
+    uint32_t miss = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        dst[j] = ~0u;
+        q[j] = ~0u;
+        if (full || p < n) {
+            const uint32_t rid = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u), rank = mt[j] >> 16;
+            const uint32_t d = run_dest[lo + rid] + rank;
+            dst[j] = (d < (uint32_t)n && rid == (mt[j] & 0xffffu)) ? d : ~0u;
+            if (STAGE) {
+                const uint32_t qq = (run_info[lo + rid] & 0xffffu) + rank;
+                q[j] = qq < (uint32_t)cnt ? qq : ~0u;
+                if (q[j] == ~0u) dst[j] = ~0u;
+            }
+            if (dst[j] == ~0u) miss = 1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        if (!(full || p < n)) continue;
+        int ii = 0;
+        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+        const DevInst &in = MULTI ? t.inst[ii] : in0;
+        const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+        const double dt = (MULTI && da) ? da[ii] : dt0;
+        push_one<D, SCHEME, REG, false, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
+    }
+    if (miss) flag_status(t.status, PIC_DEV_RANGE);
+    if (!STAGE) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            if (dst[j] == ~0u) continue;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                out.x[k][dst[j]] = xv[j][k];
+                out.v[k][dst[j]] = vv[j][k];
+            }
+        }
+        for (int c = 0; c < extra.n; ++c) {
+            if (extra.bytes[c] == 8) {
+                const uint64_t *src = (const uint64_t *)extra.in[c];
+                uint64_t *o = (uint64_t *)extra.out[c];
+                uint64_t v[IPT];
+#pragma unroll
+                for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
+#pragma unroll
+                for (int j = 0; j < IPT; ++j)
+                    if (dst[j] != ~0u) o[dst[j]] = v[j];
+            } else {
+                const uint32_t *src = (const uint32_t *)extra.in[c];
+                uint32_t *o = (uint32_t *)extra.out[c];
+                uint32_t v[IPT];
+#pragma unroll
+                for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
+#pragma unroll
+                for (int j = 0; j < IPT; ++j)
+                    if (dst[j] != ~0u) o[dst[j]] = v[j];
+            }
+        }
+        return;
+    }
+    __syncthreads();   // s_dst cleared
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+        if (dst[j] != ~0u) s_dst[q[j]] = dst[j];
+    // the 2D state columns, then the extra columns, each staged once
+    for (int c = 0; c < 2 * D + extra.n; ++c) {
+        const bool st = c < 2 * D;
+        const int e = c - 2 * D;
+        const bool wide = st || extra.bytes[e] == 8;
+        if (st) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u) s_val[q[j]] = __double_as_longlong(c < D ? xv[j][c] : vv[j][c - D]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u)
+                    s_val[q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
+                                       : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
+        }
+        __syncthreads();
+        void *o = st ? (void *)(c < D ? out.x[c] : out.v[c - D]) : extra.out[e];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int qq = tid + i * RB_THREADS;
+            if (qq >= cnt) break;
+            const uint32_t d = s_dst[qq];
+            if (d == ~0u) continue;
+            if (wide) ((uint64_t *)o)[d] = s_val[qq];
+            else ((uint32_t *)o)[d] = (uint32_t)s_val[qq];
+        }
+        __syncthreads();
+    }
+}
+
 // Zero the per-call counters and, when the input is sorted, find the old bins
 // covering each tile (one kernel instead of two).
 __global__ void k_rebin_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_start, int64_t n_bins, int64_t n,
@@ -1902,7 +2185,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
-        list, scan_state, scan_ctr, run_wcnt, total;
+        list, scan_state, scan_ctr, run_wcnt, meta, total;
 };
 
 static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
@@ -1927,6 +2210,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.list_off = o; o = align256(o + (keys + 1) * 4);
     L.list = o; o = align256(o + slots * 4);
     L.run_wcnt = o; o = align256(o + slots * 8);
+    L.meta = o; o = align256(o + slots * 4);
     L.total = o;
     return L;
 }
@@ -1986,6 +2270,7 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.scan_state = (uint64_t *)(base + L.scan_state);
     sc.scan_ctr = (uint32_t *)(base + L.scan_ctr);
     sc.run_wcnt = (uint64_t *)(base + L.run_wcnt);
+    sc.meta = (uint32_t *)(base + L.meta);
     return sc;
 }
 
@@ -2050,6 +2335,22 @@ template <int D, int SCH, bool REG, bool MULTI, int IPT>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + StepShape<IPT>::TILE - 1) / StepShape<IPT>::TILE;
+    if (g_tune.step_rank) {
+        if (a.n > 0)
+            PIC_LAUNCH("step_rank", (k_step_rank<D, SCH, REG, MULTI, IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
+                       t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc,
+                       sc.meta, g_tune.xcd_tiles);
+        launch_rebin_middle(t, a.n, a.n_bins, StepShape<IPT>::TILE, sc, new_start, s);
+        if (a.n > 0 && g_tune.emit_stage)
+            PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, IPT, true>), dim3(tiles), dim3(RB_THREADS), 0, s,
+                       t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,
+                       (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, g_tune.xcd_tiles);
+        else if (a.n > 0)
+            PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, IPT, false>), dim3(tiles), dim3(RB_THREADS), 0, s,
+                       t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,
+                       (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, g_tune.xcd_tiles);
+        return;
+    }
     if (a.n > 0)
         PIC_LAUNCH("step_count", (k_step_count<D, SCH, REG, MULTI, IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
                    t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc);
