@@ -347,18 +347,23 @@ pic_status pic_profile_only(const char *name);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
  *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048);
  *   "step_rank"     pic_step's passes: 1 = the first pass ranks every particle inside
- *                   its tile and the second only pushes and writes, 0 = the first
- *                   pass only counts and the second ranks (default 1);
- *   "xcd_tiles"     1 = pic_step's tiles are dealt to the chip's 8 XCDs in contiguous
- *                   chunks, 0 = in block order (default 1);
- *   "emit_stage"    1 = the writing pass of pic_step stages each column through LDS
- *                   in tile-sorted order, 0 = it stores straight from registers
- *                   (default 1);
+ *                   its tile and the second only pushes and writes, 2 = as 1 with the
+ *                   first pass split into a push pass that writes keys and a tile
+ *                   ranking pass over those keys, 0 = the first pass only counts and
+ *                   the second ranks (default 2);
+ *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's
+ *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
+ *   "emit_stage"    the writing pass of pic_step stages 1 or 2 columns at a time
+ *                   through LDS in tile-sorted order, or 0 = stores straight from
+ *                   registers (default 1);
+ *   "emit_threads"  threads per block of that pass, 256 or 512 (default 512);
  *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
  *                   regular instances (up to 2^21 cells per level), which the
  *                   arithmetic kernels and the FP32 form use; 0 = none, every
  *                   tree takes the descent kernels (default 1).
- * Every setting gives the same results; pic_scratch_bytes covers all of them.
+ * Every setting gives the same bins, order and particle state; "deposit_lanes"
+ * changes the order of the deposit's sums, so the charge differs in rounding
+ * only (far inside the stated tolerance).  pic_scratch_bytes covers all settings.
  * Affects calls enqueued afterwards.  Unknown names or values: PIC_E_ARG
  * (pic_tune_get returns -1).
  */

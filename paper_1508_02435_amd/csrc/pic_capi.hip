@@ -547,14 +547,17 @@ pic_status pic_tune_set(const char *name, int64_t value) {
         if (value != 0 && value != 1) return PIC_E_ARG;
         g_tune.scatter_nt = (int)value;
     } else if (k == "step_rank") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
+        if (value < 0 || value > 2) return PIC_E_ARG;
         g_tune.step_rank = (int)value;
     } else if (k == "xcd_tiles") {
         if (value != 0 && value != 1) return PIC_E_ARG;
         g_tune.xcd_tiles = (int)value;
     } else if (k == "emit_stage") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
+        if (value < 0 || value > 2) return PIC_E_ARG;
         g_tune.emit_stage = (int)value;
+    } else if (k == "emit_threads") {
+        if (value != 256 && value != 512) return PIC_E_ARG;
+        g_tune.emit_threads = (int)value;
     } else {
         return PIC_E_ARG;
     }
@@ -575,6 +578,7 @@ int64_t pic_tune_get(const char *name) {
     if (k == "step_rank") return g_tune.step_rank;
     if (k == "xcd_tiles") return g_tune.xcd_tiles;
     if (k == "emit_stage") return g_tune.emit_stage;
+    if (k == "emit_threads") return g_tune.emit_threads;
     return -1;
 }
 

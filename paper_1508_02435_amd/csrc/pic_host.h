@@ -104,9 +104,10 @@ struct Tuning {
     int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
     int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
     int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
-    int step_rank = 1;      // fused step: 1 = rank + emit passes, 0 = count + move passes
+    int step_rank = 2;      // fused step: 2 = key + group + emit, 1 = rank + emit, 0 = count + move
     int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
-    int emit_stage = 1;     // 1 = emit pass writes through LDS in tile-sorted order, 0 = direct stores
+    int emit_stage = 1;     // emit pass: columns staged through LDS per barrier (1 or 2), 0 = direct stores
+    int emit_threads = 512; // threads per emit block: 256 or 512
     int regular_tables = 1; // build Peano rank tables for regular instances of trees created afterwards
 };
 extern Tuning g_tune;

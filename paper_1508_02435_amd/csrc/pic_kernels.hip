@@ -49,6 +49,13 @@ __device__ __forceinline__ T ld_off(const T *base, uint32_t idx) {
     return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
 }
 
+// Load through the constant address space: with a wavefront-uniform address
+// it becomes a scalar load, which takes no vector memory instruction.  Only
+// for data no kernel of the launch writes.
+__device__ __forceinline__ double ld_const(const double *p, uint32_t idx) {
+    return ((const __attribute__((address_space(4))) double *)p)[idx];
+}
+
 // Scaled coordinate of one axis.  y = fl(x * S) is the only rounding on the
 // way to the cell; T = floor(2y) resolves half cells (dual-cell faces).  The
 // clamp keeps indices in range for malformed input (which is flagged).
@@ -266,12 +273,43 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
         w[c] = wc;
     }
+    // Field at the corners.  Particles are stored by bin, so the lanes of a
+    // wavefront mostly share one or two cells: up to two passes serve the
+    // lanes whose cell is that of the first pending lane (the id of corner 0
+    // names the cell) with scalar loads, and only the lanes left gather per
+    // lane.  The values, and so the arithmetic, are the same either way.
+    double Ec[1 << D][D];
+    uint64_t pend = __ballot(1);
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        if (!pend) break;
+        const int l = __builtin_ctzll(pend);
+        const uint32_t v0u = (uint32_t)__builtin_amdgcn_readlane((int)vid[0], l);
+        const bool mine = vid[0] == v0u;
+        pend &= ~__ballot(mine);
+        uint32_t vu[1 << D];
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) vu[c] = (uint32_t)__builtin_amdgcn_readlane((int)vid[c], l);
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const double eu = ld_const(P.E[j], vu[c]);
+                if (mine) Ec[c][j] = eu;
+            }
+    }
+    if ((pend >> lane) & 1ull) {
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Ec[c][j] = ld_off(P.E[j], vid[c]);
+    }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const double *Ej = P.E[j];
-        double e = __dmul_rn(w[0], ld_off(Ej, vid[0]));
+        double e = __dmul_rn(w[0], Ec[0][j]);
 #pragma unroll
-        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], ld_off(Ej, vid[c])));
+        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ec[c][j]));
         if (EP && P.Ep[0]) P.Ep[j][p] = e;
         double vj = __dadd_rn(vv[j], __dmul_rn(qmdt, e));
         double xj = __dadd_rn(xv[j], __dmul_rn(vj, dt));
@@ -389,6 +427,7 @@ struct RebinScratch {
     uint32_t *scan_ctr;   // dynamic block counter (zeroed per call)
     uint64_t *run_wcnt;   // n_tiles * TILE: fused step, 16-bit count per wavefront
     uint32_t *meta;       // n_tiles * TILE: fused step, run index | rank << 16 per particle
+    uint32_t *keys;       // n_tiles * TILE: fused step (three-pass form), key per particle
 };
 
 // Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
@@ -1279,67 +1318,65 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int on) {
     return x * q + (x < r ? x : r) + k;
 }
 
-template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
-__global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
-                                                         double qmdt0, double dt0, const double *qa,
-                                                         const double *da, const int64_t *inst_start,
-                                                         const int64_t *old_start, uint32_t n_bins,
-                                                         RebinScratch sc, uint32_t *meta, int xcd) {
-    using RS = RankShape<IPT>;
-    __shared__ uint32_t s_key[RS::H];            // key + 1 (0: empty); run index after compaction
-    __shared__ uint16_t s_wc[4][RS::H];          // per wavefront count of each slot, then its offset
-    __shared__ uint8_t s_tag[4][RS::H];          // per wavefront representative lane of each slot
-    __shared__ unsigned long long s_msk[4][64];  // per wavefront lane mask of each representative
-    __shared__ uint32_t s_wsum[4];
-    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t tiles = gridDim.x;
-    const int64_t tile = xcd_tile(blockIdx.x, tiles, xcd);
-    const int64_t lo = tile * RS::TILE;
-    for (int i = tid; i < RS::H; i += RB_THREADS) {
-        s_key[i] = 0u;
+// LDS of the tile ranking.
+template <int IPT>
+struct RankSmem {
+    uint32_t key[RankShape<IPT>::H];            // key + 1 (0: empty); run index after compaction
+    uint16_t wc[4][RankShape<IPT>::H];          // per wavefront count of each slot, then its offset
+    uint8_t tag[4][RankShape<IPT>::H];          // per wavefront representative lane of each slot
+    unsigned long long msk[4][64];              // per wavefront lane mask of each representative
+    uint32_t wsum[4];
+};
+
+template <int IPT>
+__device__ __forceinline__ void rank_clear(RankSmem<IPT> &S) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < RankShape<IPT>::H; i += RB_THREADS) {
+        S.key[i] = 0u;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) s_wc[v][i] = 0;
+        for (int v = 0; v < 4; ++v) S.wc[v][i] = 0;
     }
-    s_msk[w][lane] = 0ull;
-    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
-    double xv[IPT][D], vv[IPT][D];
-    uint32_t key[IPT];
-    uint32_t bad = 0;
-    step_push_tile<D, SCHEME, REG, MULTI, IPT>(t, in0, P, n, lo, qmdt0, dt0, qa, da, inst_start, old_start, n_bins,
-                                               lds, lds_n, xv, vv, key, bad);
-    if (bad) flag_status(t.status, bad);
-    __syncthreads();   // table cleared
+    S.msk[tid >> 6][tid & 63] = 0ull;
+}
+
+// Ranks the tile's keys (slot w*64*IPT + j*64 + lane of thread (w, lane),
+// ~0 past the end): writes the tile's runs (key, tile-local start | count <<
+// 16), adds the per-key counts, and stores run index | rank << 16 for every
+// particle.  The table must be cleared and all threads past a barrier.
+template <int IPT>
+__device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key)[IPT], int64_t tile, int64_t lo,
+                                          const RebinScratch &sc, uint32_t *meta) {
+    using RS = RankShape<IPT>;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t slot[IPT], rk[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         slot[j] = 0u;
         if (key[j] != ~0u) {
-            slot[j] = table_find<RS::HB>(s_key, key[j]);
-            if (slot[j] == ~0u) slot[j] = table_insert<RS::HB>(s_key, key[j]);
+            slot[j] = table_find<RS::HB>(S.key, key[j]);
+            if (slot[j] == ~0u) slot[j] = table_insert<RS::HB>(S.key, key[j]);
         }
     }
-    volatile uint8_t *tag = s_tag[w];
-    volatile unsigned long long *msk = s_msk[w];
-    volatile uint16_t *wc = s_wc[w];
+    // wavefront-scope atomic loads and stores: plain LDS accesses that the
+    // compiler may neither forward nor reorder against the other lanes' ones
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         rk[j] = 0u;
         if (key[j] == ~0u) continue;
-        tag[slot[j]] = (uint8_t)lane;
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t rep = tag[slot[j]];
-        atomicOr((unsigned long long *)&msk[rep], 1ull << lane);
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t m = msk[rep];
-        const uint32_t base = wc[slot[j]];
-        __builtin_amdgcn_wave_barrier();
+        uint8_t *tg = &S.tag[w][slot[j]];
+        uint16_t *cw = &S.wc[w][slot[j]];
+        __hip_atomic_store(tg, (uint8_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t rep = __hip_atomic_load(tg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        unsigned long long *mk = &S.msk[w][rep];
+        __hip_atomic_fetch_or(mk, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint64_t m = __hip_atomic_load(mk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t base = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const uint32_t below = lanes_below(m);
         if (below == 0u) {
-            wc[slot[j]] = (uint16_t)(base + (uint32_t)__popcll(m));
-            msk[rep] = 0ull;
+            __hip_atomic_store(cw, (uint16_t)(base + (uint32_t)__popcll(m)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_store(mk, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
-        __builtin_amdgcn_wave_barrier();
         rk[j] = base + below;
     }
     __syncthreads();
@@ -1350,20 +1387,20 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         const int i = tid * IPT + e;
-        k1[e] = s_key[i];
+        k1[e] = S.key[i];
         tot[e] = 0;
         if (k1[e]) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const uint32_t c = s_wc[v][i];
-                s_wc[v][i] = (uint16_t)tot[e];
+                const uint32_t c = S.wc[v][i];
+                S.wc[v][i] = (uint16_t)tot[e];
                 tot[e] += c;
             }
             packed += 1u + (tot[e] << 16);
         }
     }
     uint32_t total;
-    const uint32_t ex = block_excl_scan(packed, s_wsum, &total);
+    const uint32_t ex = block_excl_scan(packed, S.wsum, &total);
     uint32_t ri = ex & 0xffffu, lb = ex >> 16;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
@@ -1372,7 +1409,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0
         sc.run_info[lo + ri] = lb | (tot[e] << 16);
         atomicAdd(&sc.key_cnt[k1[e] - 1u], tot[e]);
         atomicAdd(&sc.key_nruns[k1[e] - 1u], 1u);
-        s_key[tid * IPT + e] = ri;
+        S.key[tid * IPT + e] = ri;
         ++ri;
         lb += tot[e];
     }
@@ -1382,26 +1419,102 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         if (key[j] == ~0u) continue;
-        meta[pbase + 64 * j] = s_key[slot[j]] | ((s_wc[w][slot[j]] + rk[j]) << 16);
+        meta[pbase + 64 * j] = S.key[slot[j]] | ((S.wc[w][slot[j]] + rk[j]) << 16);
     }
 }
 
-// Emit pass: slot p of tile T writes its pushed state to
-// run_dest[T's run area + rid] + rank.  With STAGE the tile's records are
-// first put in tile-local sorted order (runs one after the other, each run at
-// its start from the run table) through LDS, one column at a time, so that a
-// wavefront's stores cover consecutive destinations of a few runs instead of
-// a few elements of each of many runs.
-template <int D, int SCHEME, bool REG, bool MULTI, int IPT, bool STAGE>
-__global__ __launch_bounds__(RB_THREADS) void k_step_emit(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_rank(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
                                                          double qmdt0, double dt0, const double *qa,
                                                          const double *da, const int64_t *inst_start,
-                                                         const uint32_t *meta, const uint32_t *run_dest,
-                                                         const uint32_t *run_info, F64Ptrs out, Cols extra,
-                                                         int xcd) {
-    constexpr int TILE = RB_THREADS * IPT;
+                                                         const int64_t *old_start, uint32_t n_bins,
+                                                         RebinScratch sc, uint32_t *meta, int xcd) {
+    using RS = RankShape<IPT>;
+    __shared__ RankSmem<IPT> S;
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
-    __shared__ uint64_t s_val[STAGE ? TILE : 1];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, xcd);
+    const int64_t lo = tile * RS::TILE;
+    rank_clear<IPT>(S);
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    double xv[IPT][D], vv[IPT][D];
+    uint32_t key[IPT];
+    uint32_t bad = 0;
+    step_push_tile<D, SCHEME, REG, MULTI, IPT>(t, in0, P, n, lo, qmdt0, dt0, qa, da, inst_start, old_start, n_bins,
+                                               lds, lds_n, xv, vv, key, bad);
+    if (bad) flag_status(t.status, bad);
+    __syncthreads();   // table cleared
+    tile_rank<IPT>(S, key, tile, lo, sc, meta);
+}
+
+// Key pass of the three-pass form: one particle per thread, pushed, its key
+// 2*bin + arrived written out (the state itself is not).
+template <int D, int SCHEME, bool REG, bool MULTI>
+__global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
+                                                  double dt0, const double *qa, const double *da,
+                                                  const int64_t *inst_start, const int64_t *old_start,
+                                                  uint32_t n_bins, uint32_t *key_out) {
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        int ii = 0;
+        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+        const DevInst &in = MULTI ? t.inst[ii] : in0;
+        const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+        const double dt = (MULTI && da) ? da[ii] : dt0;
+        uint32_t bad = 0;
+        double xv[D], vv[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xv[k] = P.x[k][p];
+            vv[k] = P.v[k][p];
+        }
+        uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
+        if (b >= n_bins) bad |= PIC_DEV_RANGE;
+        b = min(b, n_bins - 1);
+        bool stay = false;
+        if (old_start) stay = old_start[b] <= p && p < old_start[b + 1];
+        key_out[p] = 2u * b + (stay ? 0u : 1u);
+        if (bad) flag_status(t.status, bad);
+    }
+}
+
+// Group pass of the three-pass form: the tile ranking of k_step_rank over
+// keys read from memory.
+template <int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_group(const uint32_t *keys, int64_t n, RebinScratch sc,
+                                                          uint32_t *meta, int xcd) {
+    using RS = RankShape<IPT>;
+    __shared__ RankSmem<IPT> S;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, xcd);
+    const int64_t lo = tile * RS::TILE;
+    rank_clear<IPT>(S);
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    uint32_t key[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) key[j] = base + 64 * j < n ? keys[base + 64 * j] : ~0u;
+    __syncthreads();   // table cleared
+    tile_rank<IPT>(S, key, tile, lo, sc, meta);
+}
+
+// Emit pass: slot p of tile T writes its pushed state to
+// run_dest[T's run area + rid] + rank.  NT threads cover the TILE slots of a
+// tile.  With STAGE the tile's records are first put in tile-local sorted
+// order (runs one after the other, each run at its start from the run table)
+// through LDS, STAGE columns at a time, so that a wavefront's stores cover
+// consecutive destinations of a few runs instead of a few elements of each of
+// many runs.
+template <int D, int SCHEME, bool REG, bool MULTI, int TILE, int NT, int STAGE>
+__global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
+                                                  double dt0, const double *qa, const double *da,
+                                                  const int64_t *inst_start, const uint32_t *meta,
+                                                  const uint32_t *run_dest, const uint32_t *run_info, F64Ptrs out,
+                                                  Cols extra, int xcd) {
+    constexpr int IPT = TILE / NT;
+    constexpr int NS = STAGE > 0 ? STAGE : 1;
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    __shared__ uint64_t s_val[STAGE ? NS : 1][STAGE ? TILE : 1];
     __shared__ uint32_t s_dst[STAGE ? TILE : 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
@@ -1409,7 +1522,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_emit(DevTree t, DevInst in0
     const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
     const int cnt = (int)min((int64_t)TILE, n - lo);
     if (STAGE)
-        for (int i = tid; i < TILE; i += RB_THREADS) s_dst[i] = ~0u;
+        for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
     double xv[IPT][D], vv[IPT][D];
     uint32_t mt[IPT], dst[IPT], q[IPT];
     uint32_t bad = 0;
@@ -1492,32 +1605,44 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_emit(DevTree t, DevInst in0
 #pragma unroll
     for (int j = 0; j < IPT; ++j)
         if (dst[j] != ~0u) s_dst[q[j]] = dst[j];
-    // the 2D state columns, then the extra columns, each staged once
-    for (int c = 0; c < 2 * D + extra.n; ++c) {
-        const bool st = c < 2 * D;
-        const int e = c - 2 * D;
-        const bool wide = st || extra.bytes[e] == 8;
-        if (st) {
+    // the 2D state columns, then the extra columns, NS at a time
+    const int ncol = 2 * D + extra.n;
+    for (int c0 = 0; c0 < ncol; c0 += NS) {
 #pragma unroll
-            for (int j = 0; j < IPT; ++j)
-                if (dst[j] != ~0u) s_val[q[j]] = __double_as_longlong(c < D ? xv[j][c] : vv[j][c - D]);
-        } else {
+        for (int g = 0; g < NS; ++g) {
+            const int c = c0 + g;
+            if (c >= ncol) break;
+            if (c < 2 * D) {
 #pragma unroll
-            for (int j = 0; j < IPT; ++j)
-                if (dst[j] != ~0u)
-                    s_val[q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
-                                       : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
+                for (int j = 0; j < IPT; ++j)
+                    if (dst[j] != ~0u) s_val[g][q[j]] = __double_as_longlong(c < D ? xv[j][c] : vv[j][c - D]);
+            } else {
+                const int e = c - 2 * D;
+                const bool wide = extra.bytes[e] == 8;
+#pragma unroll
+                for (int j = 0; j < IPT; ++j)
+                    if (dst[j] != ~0u)
+                        s_val[g][q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
+                                              : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
+            }
         }
         __syncthreads();
-        void *o = st ? (void *)(c < D ? out.x[c] : out.v[c - D]) : extra.out[e];
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const int qq = tid + i * RB_THREADS;
-            if (qq >= cnt) break;
-            const uint32_t d = s_dst[qq];
-            if (d == ~0u) continue;
-            if (wide) ((uint64_t *)o)[d] = s_val[qq];
-            else ((uint32_t *)o)[d] = (uint32_t)s_val[qq];
+        for (int g = 0; g < NS; ++g) {
+            const int c = c0 + g;
+            if (c >= ncol) break;
+            const bool st = c < 2 * D;
+            const bool wide = st || extra.bytes[c - 2 * D] == 8;
+            void *o = st ? (void *)(c < D ? out.x[c] : out.v[c - D]) : extra.out[c - 2 * D];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int qq = tid + i * NT;
+                if (qq >= cnt) break;
+                const uint32_t d = s_dst[qq];
+                if (d == ~0u) continue;
+                if (wide) ((uint64_t *)o)[d] = s_val[g][qq];
+                else ((uint32_t *)o)[d] = (uint32_t)s_val[g][qq];
+            }
         }
         __syncthreads();
     }
@@ -2185,7 +2310,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
-        list, scan_state, scan_ctr, run_wcnt, meta, total;
+        list, scan_state, scan_ctr, run_wcnt, meta, keys, total;
 };
 
 static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
@@ -2211,6 +2336,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.list = o; o = align256(o + slots * 4);
     L.run_wcnt = o; o = align256(o + slots * 8);
     L.meta = o; o = align256(o + slots * 4);
+    L.keys = o; o = align256(o + slots * 4);
     L.total = o;
     return L;
 }
@@ -2271,6 +2397,7 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.scan_ctr = (uint32_t *)(base + L.scan_ctr);
     sc.run_wcnt = (uint64_t *)(base + L.run_wcnt);
     sc.meta = (uint32_t *)(base + L.meta);
+    sc.keys = (uint32_t *)(base + L.keys);
     return sc;
 }
 
@@ -2331,24 +2458,40 @@ struct StepArgs {
     uint32_t n_bins;
 };
 
+#define PIC_EMIT(NT, ST)                                                                                      \
+    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, ST>), dim3(tiles), dim3(NT), 0, s, t->dt,  \
+               t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,          \
+               (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, g_tune.xcd_tiles)
+
+template <int D, int SCH, bool REG, bool MULTI, int TILE>
+static void launch_emit(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
+                        int64_t tiles, hipStream_t s) {
+    const int st = g_tune.emit_stage;
+    if (g_tune.emit_threads == 512) {
+        if (st == 2) PIC_EMIT(512, 2); else if (st == 1) PIC_EMIT(512, 1); else PIC_EMIT(512, 0);
+    } else {
+        if (st == 2) PIC_EMIT(256, 2); else if (st == 1) PIC_EMIT(256, 1); else PIC_EMIT(256, 0);
+    }
+}
+
 template <int D, int SCH, bool REG, bool MULTI, int IPT>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + StepShape<IPT>::TILE - 1) / StepShape<IPT>::TILE;
     if (g_tune.step_rank) {
-        if (a.n > 0)
+        if (a.n > 0 && g_tune.step_rank == 2) {
+            PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0,
+                       s, t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
+                       sc.keys);
+            PIC_LAUNCH("step_group", (k_step_group<IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
+                       (const uint32_t *)sc.keys, a.n, sc, sc.meta, 0);
+        } else if (a.n > 0) {
             PIC_LAUNCH("step_rank", (k_step_rank<D, SCH, REG, MULTI, IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
                        t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc,
-                       sc.meta, g_tune.xcd_tiles);
+                       sc.meta, 0);
+        }
         launch_rebin_middle(t, a.n, a.n_bins, StepShape<IPT>::TILE, sc, new_start, s);
-        if (a.n > 0 && g_tune.emit_stage)
-            PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, IPT, true>), dim3(tiles), dim3(RB_THREADS), 0, s,
-                       t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,
-                       (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, g_tune.xcd_tiles);
-        else if (a.n > 0)
-            PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, IPT, false>), dim3(tiles), dim3(RB_THREADS), 0, s,
-                       t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,
-                       (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, g_tune.xcd_tiles);
+        if (a.n > 0) launch_emit<D, SCH, REG, MULTI, StepShape<IPT>::TILE>(t, a, sc, extra, tiles, s);
         return;
     }
     if (a.n > 0)

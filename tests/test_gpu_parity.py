@@ -312,6 +312,45 @@ def test_fused_step_matches_oracle(name, scheme, kind):
     assert t.status_sync() == 0
 
 
+STEP_FORMS = [dict(step_rank=r, emit_stage=st, emit_threads=nt, xcd_tiles=x, step_tile=tl)
+              for r in (2, 1) for st in (1, 2, 0) for nt in (512, 256) for x in (1, 0) for tl in (2048,)]
+STEP_FORMS += [dict(step_rank=r, step_tile=1024) for r in (2, 1, 0)] + [dict(step_rank=0, step_tile=2048)]
+
+
+@pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
+@pytest.mark.parametrize("name,scheme", [("config1", 0), ("small_adaptive", 1), ("small_3d", 0)])
+def test_fused_step_forms_match_oracle(name, scheme, knobs):
+    """Every pass form and launch shape of pic_step: two teacher-forced steps
+    against the oracle (bins, order, state bit-exact; charge within 1e-12)."""
+    dev = _dev()
+    saved = pic.tuning()
+    try:
+        for k, v in knobs.items():
+            pic.tune(k, v)
+        wl = W.by_name(name)
+        o = oracle.OracleTree(wl.tree)
+        t = _tree(wl.tree)
+        rng = np.random.default_rng(5)
+        st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, ids=np.arange(wl.n, dtype=np.int64), device=dev)
+        st.initial_sort()
+        xs, vs, qs, start, ids = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+        for it, kind in enumerate(("random", "physical")):
+            E = _field(o, wl, rng, kind)
+            st.step_fused(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
+            r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+            torch.cuda.synchronize()
+            ids = ids[r["perm"]]
+            assert np.array_equal(st.start.cpu().numpy(), r["bin_start"]), f"offsets differ at step {it}"
+            assert np.array_equal(st.ids.cpu().numpy(), ids), f"order differs at step {it}"
+            assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+            _check_rho(st.rho.cpu().numpy(), r["rho"])
+            xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
+        assert t.status_sync() == 0
+    finally:
+        for k, v in saved.items():
+            pic.tune(k, v)
+
+
 @pytest.mark.parametrize("spread", [0.05, 0.5])
 @pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 5 * 2048 + 3])
