@@ -403,6 +403,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
 // ------------------------------------------------------------------- rebin
 
 constexpr int RB_THREADS = 256;
+constexpr int KLIST_CAP = 64;   // runs per key listed directly by the fused step's ranking
 constexpr int RB_MAX_TILE = 4096;
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -428,6 +429,9 @@ struct RebinScratch {
     uint64_t *run_wcnt;   // n_tiles * TILE: fused step, 16-bit count per wavefront
     uint32_t *meta;       // n_tiles * TILE: fused step, run index | rank << 16 per particle
     uint32_t *keys;       // n_tiles * TILE: fused step (three-pass form), key per particle
+    uint32_t *klist;      // 2*n_bins * KLIST_CAP: fused step, run addresses per key (arrival order)
+    uint32_t *khead;      // 2*n_bins (zeroed per call): runs of a key past KLIST_CAP, a linked list
+    uint32_t *knext;      // n_tiles * TILE: next run of that list (run address + 1; 0 ends it)
 };
 
 // Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
@@ -766,10 +770,11 @@ __global__ __launch_bounds__(256) void k_rebin_lists(RebinScratch sc, int tile_s
 // lists are then handled by the whole wavefront: up to 64 runs with a 64-lane
 // bitonic sort, beyond that by counting the smaller addresses per run.
 template <int W>
-__device__ __forceinline__ void place_sorted(RebinScratch &sc, uint32_t l0, uint32_t len, uint32_t kb, int sub) {
+__device__ __forceinline__ void place_sorted(const RebinScratch &sc, const uint32_t *lst, uint32_t l0, uint32_t len,
+                                             uint32_t kb, int sub) {
     uint32_t a = 0xffffffffu, c = 0;
     if ((uint32_t)sub < len) {
-        a = sc.list[l0 + sub];
+        a = lst[l0 + sub];
         c = sc.run_info[a] >> 16;
     }
 #pragma unroll
@@ -806,7 +811,7 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc, uint32_t n
             len = sc.list_off[key + 1] - l0;
             kb = sc.key_base[key];
         }
-        if (len <= 16) place_sorted<16>(sc, l0, len, kb, sub);   // len 0: nothing written
+        if (len <= 16) place_sorted<16>(sc, sc.list, l0, len, kb, sub);   // len 0: nothing written
         // keys with longer lists: whole wavefront, one after the other
         for (int g = 0; g < 4; ++g) {
             const uint32_t gl0 = (uint32_t)__shfl((int)l0, g * 16, 64);
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc, uint32_t n
             const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
             if (glen <= 16) continue;
             if (glen <= 64) {
-                place_sorted<64>(sc, gl0, glen, gkb, lane);
+                place_sorted<64>(sc, sc.list, gl0, glen, gkb, lane);
             } else {
                 for (uint32_t q = lane; q < glen; q += 64) {
                     const uint32_t a = sc.list[gl0 + q];
@@ -825,6 +830,151 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc, uint32_t n
                     }
                     sc.run_dest[a] = gkb + before;
                 }
+            }
+        }
+    }
+}
+
+// Fused step, middle.  Scan: each block of SP_THREADS threads scans the
+// (count, runs) pairs of SP_KEYS keys; its first wavefront publishes the
+// block's aggregate and looks back over up to 64 predecessors at a time (one
+// lane per predecessor) for the exclusive prefix.  Place: per key, its runs
+// (the direct list the ranking filled, then for keys with more than KLIST_CAP
+// runs the linked rest) sorted by run address, i.e. tile order, and given
+// their destinations.
+constexpr int SP_THREADS = 256;
+constexpr int SP_KPT = 8;                       // keys per thread
+constexpr int SP_KEYS = SP_THREADS * SP_KPT;
+
+__global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint32_t n_bins, int64_t n, RebinScratch sc,
+                                                          int64_t *new_start, uint32_t *status) {
+    __shared__ uint32_t s_bid;
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint64_t s_excl;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_bid = atomicAdd(sc.scan_ctr, 1u);
+    __syncthreads();
+    const uint32_t bid = s_bid;
+    const uint64_t k0 = (uint64_t)bid * SP_KEYS + (uint64_t)tid * SP_KPT;
+    uint32_t c[SP_KPT], r[SP_KPT];
+    uint32_t cs = 0, rs = 0;
+#pragma unroll
+    for (int j = 0; j < SP_KPT; ++j) {
+        const uint64_t k = k0 + j;
+        c[j] = r[j] = 0;
+        if (k < n_keys) {
+            c[j] = sc.key_cnt[k];
+            r[j] = sc.key_nruns[k];
+        }
+        cs += c[j];
+        rs += r[j];
+    }
+    uint32_t ctot, rtot;
+    const uint32_t cex = block_excl_scan(cs, s_wsum, &ctot);
+    const uint32_t rex = block_excl_scan(rs, s_wsum, &rtot);
+    if (w == 0) {
+        const uint64_t agg = ((uint64_t)ctot << 31) | rtot;
+        uint64_t excl = 0;
+        if (bid == 0) {
+            if (lane == 0) __hip_atomic_store(&sc.scan_state[0], ST_PRE | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0) __hip_atomic_store(&sc.scan_state[bid], ST_AGG | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t ec = 0, er = 0;
+            int64_t j0 = (int64_t)bid - 1;
+            uint32_t spins = 0;
+            bool failed = false;
+            while (j0 >= 0) {
+                const int64_t j = j0 - lane;
+                uint64_t st = ST_PRE;   // before block 0: an empty prefix
+                for (;;) {
+                    if (j >= 0) st = __hip_atomic_load(&sc.scan_state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (__ballot((st >> 62) == 0) == 0) break;
+                    if (++spins > (1u << 24)) {   // bounded wait: report instead of hanging
+                        failed = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (failed) break;
+                const uint64_t pre = __ballot((st >> 62) == 2);
+                const int stop = pre ? __builtin_ctzll(pre) : 63;
+                uint64_t vc = lane <= stop ? ((st & ST_VAL) >> 31) : 0, vr = lane <= stop ? (st & 0x7fffffffull) : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    vc += (uint64_t)__shfl_xor((long long)vc, o, 64);
+                    vr += (uint64_t)__shfl_xor((long long)vr, o, 64);
+                }
+                ec += vc;
+                er += vr;
+                if (pre) break;
+                j0 -= 64;
+            }
+            if (failed && lane == 0) atomicOr(status, PIC_DEV_RANGE);
+            excl = ((ec & 0x7fffffffull) << 31) | (er & 0x7fffffffull);
+            const uint64_t incl = (((ec + ctot) & 0x7fffffffull) << 31) | ((er + rtot) & 0x7fffffffull);
+            if (lane == 0) __hip_atomic_store(&sc.scan_state[bid], ST_PRE | incl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    uint32_t cb = (uint32_t)(s_excl >> 31) + cex, rb = (uint32_t)(s_excl & 0x7fffffffull) + rex;
+#pragma unroll
+    for (int j = 0; j < SP_KPT; ++j) {
+        const uint64_t k = k0 + j;
+        if (k < n_keys) {
+            sc.key_base[k] = cb;
+            sc.list_off[k] = rb;
+            if ((k & 1) == 0) new_start[k >> 1] = cb;
+            if (k + 1 == n_keys) {
+                sc.list_off[n_keys] = rb + r[j];
+                new_start[n_bins] = n;
+            }
+        }
+        cb += c[j];
+        rb += r[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_keys) {
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, sub = lane & 15;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t k0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4; k0 < n_keys;
+         k0 += waves * 4) {
+        const int64_t key = k0 + grp;
+        uint32_t len = 0, kb = 0;
+        if (key < n_keys) {
+            len = sc.key_nruns[key];
+            kb = sc.key_base[key];
+        }
+        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * KLIST_CAP), len, kb, sub);
+        for (int g = 0; g < 4; ++g) {
+            const int64_t gk = k0 + g;
+            const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
+            const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
+            if (glen <= 16) continue;
+            if (glen <= (uint32_t)KLIST_CAP) {
+                place_sorted<64>(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane);
+                continue;
+            }
+            // a long list: gathered into its exact slot range of the list
+            // array (direct part by the lanes, linked part by lane 0), then
+            // every run counts the runs before it
+            const uint32_t l0 = sc.list_off[gk];
+            sc.list[l0 + lane] = sc.klist[gk * KLIST_CAP + lane];
+            if (lane == 0) {
+                uint32_t q = KLIST_CAP;
+                for (uint32_t e = sc.khead[gk]; e != 0u && q < glen; e = sc.knext[e - 1u]) sc.list[l0 + q++] = e - 1u;
+            }
+            __threadfence();   // lane 0's entries visible to the other lanes' loads
+            for (uint32_t q = lane; q < glen; q += 64) {
+                const uint32_t a = sc.list[l0 + q];
+                uint32_t before = 0;
+                for (uint32_t j = l0; j < l0 + glen; ++j) {
+                    const uint32_t bb = sc.list[j];
+                    if (bb < a) before += sc.run_info[bb] >> 16;
+                }
+                sc.run_dest[a] = gkb + before;
             }
         }
     }
@@ -1405,10 +1555,14 @@ __device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         if (!k1[e]) continue;
-        sc.run_key[lo + ri] = k1[e] - 1u;
+        const uint32_t k = k1[e] - 1u;
+        sc.run_key[lo + ri] = k;
         sc.run_info[lo + ri] = lb | (tot[e] << 16);
-        atomicAdd(&sc.key_cnt[k1[e] - 1u], tot[e]);
-        atomicAdd(&sc.key_nruns[k1[e] - 1u], 1u);
+        atomicAdd(&sc.key_cnt[k], tot[e]);
+        const uint32_t pos = atomicAdd(&sc.key_nruns[k], 1u);
+        const uint32_t a = (uint32_t)(lo + ri);
+        if (pos < (uint32_t)KLIST_CAP) sc.klist[(int64_t)k * KLIST_CAP + pos] = a;
+        else sc.knext[a] = atomicExch(&sc.khead[k], a + 1u);
         S.key[tid * IPT + e] = ri;
         ++ri;
         lb += tot[e];
@@ -1452,10 +1606,12 @@ template <int D, int SCHEME, bool REG, bool MULTI>
 __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const int64_t *old_start,
-                                                  uint32_t n_bins, uint32_t *key_out) {
+                                                  uint32_t n_bins, uint32_t *key_out, uint32_t *zero,
+                                                  int64_t n_zero) {
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
     const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += stride) zero[i] = 0u;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
@@ -2310,7 +2466,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
-        list, scan_state, scan_ctr, run_wcnt, meta, keys, total;
+        list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, total;
 };
 
 static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
@@ -2318,7 +2474,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     const int64_t tiles = (n + tile - 1) / tile;
     const int64_t slots = tiles * tile;
     const int64_t keys = 2 * n_bins;
-    const int64_t scan_blocks = (keys + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t scan_blocks = (keys + std::min(SP_KEYS, SCAN_TILE) - 1) / std::min(SP_KEYS, SCAN_TILE);
     size_t o = 0;
     L.tile_bin = o; o = align256(o + tiles * 8);
     L.perm = o; o = align256(o + slots * 2);
@@ -2331,12 +2487,15 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.key_fill = o; o = align256(o + keys * 4);     // them all
     L.scan_state = o; o = align256(o + scan_blocks * 8);
     L.scan_ctr = o; o = align256(o + 4);
+    L.khead = o; o = align256(o + keys * 4);
     L.key_base = o; o = align256(o + keys * 4);
     L.list_off = o; o = align256(o + (keys + 1) * 4);
     L.list = o; o = align256(o + slots * 4);
     L.run_wcnt = o; o = align256(o + slots * 8);
     L.meta = o; o = align256(o + slots * 4);
     L.keys = o; o = align256(o + slots * 4);
+    L.klist = o; o = align256(o + keys * KLIST_CAP * 4);
+    L.knext = o; o = align256(o + slots * 4);
     L.total = o;
     return L;
 }
@@ -2398,6 +2557,9 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.run_wcnt = (uint64_t *)(base + L.run_wcnt);
     sc.meta = (uint32_t *)(base + L.meta);
     sc.keys = (uint32_t *)(base + L.keys);
+    sc.klist = (uint32_t *)(base + L.klist);
+    sc.khead = (uint32_t *)(base + L.khead);
+    sc.knext = (uint32_t *)(base + L.knext);
     return sc;
 }
 
@@ -2414,6 +2576,16 @@ static void launch_rebin_middle(const pic_tree *t, int64_t n, int64_t n_bins, in
         PIC_LAUNCH("rebin_lists", k_rebin_lists, dim3(tiles), dim3(256), 0, s, sc, tile);
         PIC_LAUNCH("rebin_place", k_rebin_place, dim3(grid_for(keys, 16, 1 << 16)), dim3(256), 0, s, sc, (uint32_t)keys);
     }
+}
+
+// The middle of the fused step: scan, then placement from the per-key lists.
+static void launch_step_middle(const pic_tree *t, int64_t n, int64_t n_bins, const RebinScratch &sc,
+                               int64_t *new_start, hipStream_t s) {
+    const int64_t keys = 2 * n_bins;
+    PIC_LAUNCH("step_scan", k_step_scan, dim3((keys + SP_KEYS - 1) / SP_KEYS), dim3(SP_THREADS), 0, s, (uint32_t)keys,
+               (uint32_t)n_bins, n, sc, new_start, t->dt.status);
+    if (n > 0)
+        PIC_LAUNCH("step_place", k_step_place, dim3(grid_for(keys, 16, 1 << 16)), dim3(256), 0, s, sc, (uint32_t)keys);
 }
 
 hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t *new_bin, const int64_t *old_start,
@@ -2450,6 +2622,8 @@ hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
                           hipStream_t s);
 
 struct StepArgs {
+    uint32_t *zero;   // per-call counters, cleared by the first pass when it can
+    int64_t n_zero;
     F64Ptrs P, out;
     int64_t n;
     double qmdt, dt;
@@ -2482,7 +2656,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
         if (a.n > 0 && g_tune.step_rank == 2) {
             PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0,
                        s, t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
-                       sc.keys);
+                       sc.keys, a.zero, a.n_zero);
             PIC_LAUNCH("step_group", (k_step_group<IPT>), dim3(tiles), dim3(RB_THREADS), 0, s,
                        (const uint32_t *)sc.keys, a.n, sc, sc.meta, 0);
         } else if (a.n > 0) {
@@ -2490,7 +2664,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
                        t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, sc,
                        sc.meta, 0);
         }
-        launch_rebin_middle(t, a.n, a.n_bins, StepShape<IPT>::TILE, sc, new_start, s);
+        launch_step_middle(t, a.n, a.n_bins, sc, new_start, s);
         if (a.n > 0) launch_emit<D, SCH, REG, MULTI, StepShape<IPT>::TILE>(t, a, sc, extra, tiles, s);
         return;
     }
@@ -2536,9 +2710,13 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     char *base = (char *)scratch;
     const RebinScratch sc = bind_scratch(L, base);
     const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
-    PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(zero_words, 256, 4096)), dim3(256), 0, s,
-               (uint32_t *)(base + L.key_cnt), zero_words, nullptr, n_bins, n, tile, sc);
     StepArgs a;
+    a.zero = (uint32_t *)(base + L.key_cnt);
+    a.n_zero = zero_words;
+    // the key pass of the three-pass form clears the counters itself
+    if (!(g_tune.step_rank == 2 && n > 0))
+        PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(zero_words, 256, 4096)), dim3(256), 0, s,
+                   (uint32_t *)(base + L.key_cnt), zero_words, nullptr, n_bins, n, tile, sc);
     a.P = make_ptrs(t, in, E, nullptr);
     a.out = make_ptrs(t, out, nullptr, nullptr);
     a.n = n;

@@ -351,6 +351,39 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
             pic.tune(k, v)
 
 
+@pytest.mark.parametrize("step_rank", [2, 1])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_fused_step_with_overfull_key_lists(step_rank, scheme):
+    """Every one of 80 tiles sends particles to every bin of a 3x3 tree, so each
+    key collects more runs than its direct list holds: the general list and
+    place passes take over, and the step still matches the oracle."""
+    dev = _dev()
+    saved = pic.tuning()
+    try:
+        pic.tune("step_rank", step_rank)
+        rng = np.random.default_rng(31)
+        spec = W.regular_tree(2, 1)
+        n = 80 * 2048 + 77
+        x, v = rng.random((2, n)), rng.standard_normal((2, n)) * 0.4
+        o = oracle.OracleTree(spec)
+        t = _tree(spec)
+        E = W.random_field(rng, 2, o.n_vertices, 0.5)
+        st = pic.Stepper(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+        st.initial_sort()
+        xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+        st.step_fused(torch.tensor(E, device=dev), -0.9, 0.9, q_uniform=-1.0)
+        r = oracle.step(o, xs, vs, E, -0.9, 0.9, start, scheme, None, -1.0)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+        assert np.array_equal(st.ids.cpu().numpy(), ids[r["perm"]])
+        assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        assert t.status_sync() == 0
+    finally:
+        for k, v in saved.items():
+            pic.tune(k, v)
+
+
 @pytest.mark.parametrize("spread", [0.05, 0.5])
 @pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 5 * 2048 + 3])
