@@ -356,7 +356,7 @@ pic_status pic_profile_only(const char *name);
  *   "emit_stage"    the writing pass of pic_step stages 1 or 2 columns at a time
  *                   through LDS in tile-sorted order, or 0 = stores straight from
  *                   registers (default 1);
- *   "emit_threads"  threads per block of that pass, 256 or 512 (default 512);
+ *   "emit_threads"  threads per block of that pass, 256, 512 or 1024 (default 1024);
  *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
  *                   regular instances (up to 2^21 cells per level), which the
  *                   arithmetic kernels and the FP32 form use; 0 = none, every

@@ -556,7 +556,7 @@ pic_status pic_tune_set(const char *name, int64_t value) {
         if (value < 0 || value > 2) return PIC_E_ARG;
         g_tune.emit_stage = (int)value;
     } else if (k == "emit_threads") {
-        if (value != 256 && value != 512) return PIC_E_ARG;
+        if (value != 256 && value != 512 && value != 1024) return PIC_E_ARG;
         g_tune.emit_threads = (int)value;
     } else {
         return PIC_E_ARG;

@@ -55,6 +55,14 @@ __device__ __forceinline__ T ld_off(const T *base, uint32_t idx) {
 __device__ __forceinline__ double ld_const(const double *p, uint32_t idx) {
     return ((const __attribute__((address_space(4))) double *)p)[idx];
 }
+__device__ __forceinline__ int64_t ld_const(const int64_t *p, uint32_t idx) {
+    return ((const __attribute__((address_space(4))) int64_t *)p)[idx];
+}
+__device__ __forceinline__ uint32_t ld_const(const uint32_t *p, uint32_t idx) {
+    return ((const __attribute__((address_space(4))) uint32_t *)p)[idx];
+}
+
+__device__ __forceinline__ double x_scaled(double x, double Sd) { return __dmul_rn(x, Sd); }
 
 // Scaled coordinate of one axis.  y = fl(x * S) is the only rounding on the
 // way to the cell; T = floor(2y) resolves half cells (dual-cell faces).  The
@@ -1625,11 +1633,45 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
             xv[k] = P.x[k][p];
             vv[k] = P.v[k][p];
         }
+        // finest cell of the old position (PIT on a regular instance: its bin)
+        uint32_t cold = 0;
+        if (SCHEME == PIC_PIT && REG) {
+            uint32_t m = 1;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double y = x_scaled(xv[k], in.Sd);
+                cold += __umul24(min((uint32_t)max(y, 0.0), (uint32_t)in.S - 1u), m);
+                m = __umul24(m, (uint32_t)in.S);
+            }
+        }
         uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
         if (b >= n_bins) bad |= PIC_DEV_RANGE;
         b = min(b, n_bins - 1);
-        bool stay = false;
-        if (old_start) stay = old_start[b] <= p && p < old_start[b + 1];
+        // A particle stays iff its slot lies in its new bin's old segment.
+        // When the slot lies in the old segment of the bin of its old cell,
+        // that is the case iff the two bins agree; the lanes of a wavefront
+        // mostly share that cell, so its bin and segment come from scalar
+        // loads.  Other lanes load the new bin's segment.
+        bool stay = false, known = !old_start;
+        if (SCHEME == PIC_PIT && REG && !MULTI && old_start) {
+            uint64_t pend = __ballot(1);
+            const uint32_t lane = __lane_id();
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                if (!pend) break;
+                const uint32_t cu = (uint32_t)__builtin_amdgcn_readlane((int)cold, __builtin_ctzll(pend));
+                const bool mine = cold == cu;
+                pend &= ~__ballot(mine);
+                const uint32_t ob = (uint32_t)in.leaf_off + ld_const(t.peano_tab, (uint32_t)in.ptab + cu);
+                const int64_t s0 = ld_const(old_start, ob), s1 = ld_const(old_start, ob + 1u);
+                if (mine && s0 <= p && p < s1) {
+                    stay = b == ob;
+                    known = true;
+                }
+            }
+            (void)lane;
+        }
+        if (!known) stay = old_start[b] <= p && p < old_start[b + 1];
         key_out[p] = 2u * b + (stay ? 0u : 1u);
         if (bad) flag_status(t.status, bad);
     }
@@ -2641,7 +2683,9 @@ template <int D, int SCH, bool REG, bool MULTI, int TILE>
 static void launch_emit(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                         int64_t tiles, hipStream_t s) {
     const int st = g_tune.emit_stage;
-    if (g_tune.emit_threads == 512) {
+    if (g_tune.emit_threads == 1024) {
+        if (st == 2) PIC_EMIT(1024, 2); else if (st == 1) PIC_EMIT(1024, 1); else PIC_EMIT(1024, 0);
+    } else if (g_tune.emit_threads == 512) {
         if (st == 2) PIC_EMIT(512, 2); else if (st == 1) PIC_EMIT(512, 1); else PIC_EMIT(512, 0);
     } else {
         if (st == 2) PIC_EMIT(256, 2); else if (st == 1) PIC_EMIT(256, 1); else PIC_EMIT(256, 0);

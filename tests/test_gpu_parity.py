@@ -313,7 +313,7 @@ def test_fused_step_matches_oracle(name, scheme, kind):
 
 
 STEP_FORMS = [dict(step_rank=r, emit_stage=st, emit_threads=nt, xcd_tiles=x, step_tile=tl)
-              for r in (2, 1) for st in (1, 2, 0) for nt in (512, 256) for x in (1, 0) for tl in (2048,)]
+              for r in (2, 1) for st in (1, 2, 0) for nt in (1024, 512, 256) for x in (1, 0) for tl in (2048,)]
 STEP_FORMS += [dict(step_rank=r, step_tile=1024) for r in (2, 1, 0)] + [dict(step_rank=0, step_tile=2048)]
 
 
