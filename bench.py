@@ -57,22 +57,31 @@ def algorithmic_bytes_f32(dim: int, per_particle_q: bool):
     }
 
 
-def algorithmic_bytes(dim: int, per_particle_q: bool):
-    """Bytes each kernel must move per particle (FP64 form)."""
+def algorithmic_bytes(dim: int, per_particle_q: bool, step_rank: int = 2):
+    """Bytes each kernel must move per particle (FP64 form).  "calls" is the
+    three-call path (gather_push, rebin, deposit); "fused" is pic_step in the
+    pass form selected by the step_rank knob."""
     s_push = 2 * 8 * dim                   # x, v
     q = 8 if per_particle_q else 0
     s_rec = s_push + q                     # a full record moved by a rebin
     s_dep = 8 * dim + q                    # positions (and charges) read by the deposit
-    return {
+    ab = {
         "gather_push": 2 * s_push + 4,     # x, v read and written, new bin written
         "rebin_tiles": 4,                  # new bins read
         "rebin_scatter": 2 * s_rec,        # every record read and written once
         "deposit_bins": s_dep,
         "step_count": s_push,              # x, v read
         "step_move": s_push + s_rec + q,   # x, v (and q) read, the full record written
+        "step_key": s_push + 4,            # x, v read, key written
+        "step_group": 4 + 4,               # key read, run index | rank written
+        "step_rank": s_push + 4,           # x, v read, run index | rank written
+        "step_emit": s_push + 4 + s_rec + q,   # x, v, run index | rank (and q) read, the record written
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
-        "fused": s_push + (s_push + s_rec + q) + s_dep,   # step_count + step_move + deposit_bins
     }
+    ab["fused"] = {0: ab["step_count"] + ab["step_move"],
+                   1: ab["step_rank"] + ab["step_emit"],
+                   2: ab["step_key"] + ab["step_group"] + ab["step_emit"]}[step_rank] + s_dep
+    return ab
 
 
 def kernel_times(lib):
@@ -231,7 +240,7 @@ def run_batched(args, scheme):
     kt = kernel_times(lib)
     lib.pic_profile_enable(0)
     per_kernel = {k: {"launches": a, "avg_ms": tot / a} for k, (a, tot) in kt.items()}
-    ab = algorithmic_bytes(2, False)
+    ab = algorithmic_bytes(2, False, pic.tuning()["step_rank"])
     dominant = max((k for k in per_kernel if k in ab), key=lambda k: per_kernel[k]["avg_ms"])
     achieved = ab[dominant] * n / (per_kernel[dominant]["avg_ms"] * 1e-3) / 1e9
     del st
@@ -343,7 +352,8 @@ def main():
         raise RuntimeError("device status error during warmup")
 
     lib = pic.lib()
-    ab = (algorithmic_bytes_f32 if f32 else algorithmic_bytes)(wl.dim, wl.q is not None)
+    ab = (algorithmic_bytes_f32(wl.dim, wl.q is not None) if f32 else
+          algorithmic_bytes(wl.dim, wl.q is not None, pic.tuning()["step_rank"]))
     # per-kernel table from a profiled pass (every launch bracketed by events)
     lib.pic_profile_enable(1)
     kernel_times(lib)                       # drop anything recorded so far
@@ -386,7 +396,11 @@ def main():
                 "bytes_per_launch_algorithmic": bytes_launch,
                 "step_bytes_per_particle": step_bytes,
                 "step_algorithmic_GBps": round(step_bytes * value / 1e9, 1),
-                "step_frac": round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4)}
+                "step_frac": round(step_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
+                # the same step priced at the three-call ABI's bytes (each call streams its own
+                # inputs and outputs once), the yardstick of the 60%-of-HBM target
+                "three_call_bytes_per_particle": ab["calls"],
+                "three_call_frac": round(ab["calls"] * value / 1e9 / HBM_PEAK_GBS, 4)}
 
     stream = None
     if not args.no_stream and not f32:

@@ -140,10 +140,23 @@ __device__ __forceinline__ uint32_t descend(const DevTree &t, const DevInst &in,
 }
 
 // Instance of particle p in a forest (binary search over particle offsets).
+// The lanes of a wavefront hold consecutive slots, mostly of one instance:
+// the first active lane's instance is found with scalar loads, and only
+// lanes outside it search on their own.
 __device__ __forceinline__ int inst_of(const int64_t *start, int n_inst, int64_t p) {
+    const int l = __builtin_ctzll(__ballot(1));
+    const uint64_t pu = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)p, l)) |
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)p >> 32), l) << 32);
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
+        const int mid = (lo + hi + 1) >> 1;
+        if (ld_const(start, (uint32_t)mid) <= (int64_t)pu) lo = mid; else hi = mid - 1;
+    }
+    if (ld_const(start, (uint32_t)lo) <= p && p < ld_const(start, (uint32_t)lo + 1u)) return lo;
+    lo = 0;
+    hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
         if (start[mid] <= p) lo = mid; else hi = mid - 1;
     }
     return lo;
@@ -678,7 +691,9 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebin_tiles(const uint32_t *new_
 }
 
 // Pass 2: single-pass scan (decoupled look-back) of the per-key (count, runs)
-// pairs.  Each 64-bit state word holds flag << 62 | count << 31 | runs.
+// pairs.  Each 64-bit state word holds flag << 62 | count << 31 | runs; the
+// state words are relaxed atomics, since a block reads nothing of its
+// predecessors but those words.
 constexpr int SCAN_IPT = 8;
 constexpr int SCAN_TILE = 256 * SCAN_IPT;
 constexpr uint64_t ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_VAL = (1ull << 62) - 1;
@@ -713,13 +728,13 @@ __global__ __launch_bounds__(256) void k_rebin_scan(uint32_t n_keys, uint32_t n_
         const uint64_t agg = ((uint64_t)ctot << 31) | rtot;
         uint64_t excl = 0;
         if (bid == 0) {
-            __hip_atomic_store(&sc.scan_state[0], ST_PRE | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sc.scan_state[0], ST_PRE | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&sc.scan_state[bid], ST_AGG | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sc.scan_state[bid], ST_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int64_t j = (int64_t)bid - 1;
             uint32_t spins = 0;
             while (j >= 0) {
-                const uint64_t st = __hip_atomic_load(&sc.scan_state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t st = __hip_atomic_load(&sc.scan_state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((st >> 62) == 0) {
                     if (++spins > (1u << 26)) {   // bounded wait: report instead of hanging
                         atomicOr(status, PIC_DEV_RANGE);
@@ -736,7 +751,7 @@ __global__ __launch_bounds__(256) void k_rebin_scan(uint32_t n_keys, uint32_t n_
             }
             const uint64_t incl = ((((excl >> 31) + ctot) & 0x7fffffffull) << 31) |
                                   (((excl & 0x7fffffffull) + rtot) & 0x7fffffffull);
-            __hip_atomic_store(&sc.scan_state[bid], ST_PRE | incl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sc.scan_state[bid], ST_PRE | incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         s_excl = excl;
     }
@@ -851,18 +866,17 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinScratch sc, uint32_t n
 // runs the linked rest) sorted by run address, i.e. tile order, and given
 // their destinations.
 constexpr int SP_THREADS = 256;
-constexpr int SP_KPT = 8;                       // keys per thread
+constexpr int SP_KPT = 16;                      // keys per thread
 constexpr int SP_KEYS = SP_THREADS * SP_KPT;
 
 __global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint32_t n_bins, int64_t n, RebinScratch sc,
                                                           int64_t *new_start, uint32_t *status) {
-    __shared__ uint32_t s_bid;
+    // Blocks are dispatched in index order, so every predecessor a block
+    // waits for is already running (the wait is bounded all the same).
     __shared__ uint32_t s_wsum[4];
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_bid = atomicAdd(sc.scan_ctr, 1u);
-    __syncthreads();
-    const uint32_t bid = s_bid;
+    const uint32_t bid = blockIdx.x;
     const uint64_t k0 = (uint64_t)bid * SP_KEYS + (uint64_t)tid * SP_KPT;
     uint32_t c[SP_KPT], r[SP_KPT];
     uint32_t cs = 0, rs = 0;
@@ -880,49 +894,69 @@ __global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint3
     uint32_t ctot, rtot;
     const uint32_t cex = block_excl_scan(cs, s_wsum, &ctot);
     const uint32_t rex = block_excl_scan(rs, s_wsum, &rtot);
-    if (w == 0) {
-        const uint64_t agg = ((uint64_t)ctot << 31) | rtot;
-        uint64_t excl = 0;
-        if (bid == 0) {
-            if (lane == 0) __hip_atomic_store(&sc.scan_state[0], ST_PRE | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0) __hip_atomic_store(&sc.scan_state[bid], ST_AGG | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t ec = 0, er = 0;
-            int64_t j0 = (int64_t)bid - 1;
+    // look-back: every thread reads one of the 256 predecessors before the
+    // window start; the nearest published prefix ends the walk
+    __shared__ uint64_t s_pc[4], s_pr[4];
+    __shared__ int s_stop[4];
+    __shared__ uint32_t s_done, s_fail;
+    const uint64_t agg = ((uint64_t)ctot << 31) | rtot;
+    if (tid == 0) {
+        __hip_atomic_store(&sc.scan_state[bid], (bid == 0 ? ST_PRE : ST_AGG) | agg, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        s_done = bid == 0 ? 1u : 0u;
+        s_fail = 0u;
+    }
+    uint64_t ec = 0, er = 0;
+    __syncthreads();
+    for (int64_t j0 = (int64_t)bid - 1; !s_done; j0 -= SP_THREADS) {
+        const int64_t j = j0 - tid;
+        uint64_t st = ST_PRE;   // before block 0: an empty prefix
+        if (j >= 0) {
             uint32_t spins = 0;
-            bool failed = false;
-            while (j0 >= 0) {
-                const int64_t j = j0 - lane;
-                uint64_t st = ST_PRE;   // before block 0: an empty prefix
-                for (;;) {
-                    if (j >= 0) st = __hip_atomic_load(&sc.scan_state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    if (__ballot((st >> 62) == 0) == 0) break;
-                    if (++spins > (1u << 24)) {   // bounded wait: report instead of hanging
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+            for (;;) {
+                st = __hip_atomic_load(&sc.scan_state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((st >> 62) != 0) break;
+                if (++spins > (1u << 22)) {   // bounded wait: report instead of hanging
+                    s_fail = 1u;
+                    st = ST_PRE;
+                    break;
                 }
-                if (failed) break;
-                const uint64_t pre = __ballot((st >> 62) == 2);
-                const int stop = pre ? __builtin_ctzll(pre) : 63;
-                uint64_t vc = lane <= stop ? ((st & ST_VAL) >> 31) : 0, vr = lane <= stop ? (st & 0x7fffffffull) : 0;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    vc += (uint64_t)__shfl_xor((long long)vc, o, 64);
-                    vr += (uint64_t)__shfl_xor((long long)vr, o, 64);
-                }
-                ec += vc;
-                er += vr;
-                if (pre) break;
-                j0 -= 64;
+                __builtin_amdgcn_s_sleep(1);
             }
-            if (failed && lane == 0) atomicOr(status, PIC_DEV_RANGE);
-            excl = ((ec & 0x7fffffffull) << 31) | (er & 0x7fffffffull);
-            const uint64_t incl = (((ec + ctot) & 0x7fffffffull) << 31) | ((er + rtot) & 0x7fffffffull);
-            if (lane == 0) __hip_atomic_store(&sc.scan_state[bid], ST_PRE | incl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (lane == 0) s_excl = excl;
+        // nearest published prefix: the smallest thread index with a PRE flag
+        const uint64_t pre = __ballot((st >> 62) == 2);
+        if (lane == 0) s_stop[w] = pre ? 64 * w + __builtin_ctzll(pre) : SP_THREADS;
+        __syncthreads();
+        int stop = SP_THREADS;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) stop = min(stop, s_stop[v]);
+        uint64_t vc = tid <= stop ? ((st & ST_VAL) >> 31) : 0, vr = tid <= stop ? (st & 0x7fffffffull) : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            vc += (uint64_t)__shfl_xor((long long)vc, o, 64);
+            vr += (uint64_t)__shfl_xor((long long)vr, o, 64);
+        }
+        if (lane == 0) {
+            s_pc[w] = vc;
+            s_pr[w] = vr;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ec += s_pc[v];
+            er += s_pr[v];
+        }
+        if (tid == 0 && (stop < SP_THREADS || j0 - SP_THREADS < 0)) s_done = 1u;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (s_fail) atomicOr(status, PIC_DEV_RANGE);
+        s_excl = ((ec & 0x7fffffffull) << 31) | (er & 0x7fffffffull);
+        if (bid != 0)
+            __hip_atomic_store(&sc.scan_state[bid],
+                               ST_PRE | (((ec + ctot) & 0x7fffffffull) << 31) | ((er + rtot) & 0x7fffffffull),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     uint32_t cb = (uint32_t)(s_excl >> 31) + cex, rb = (uint32_t)(s_excl & 0x7fffffffull) + rex;
@@ -955,6 +989,7 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
             len = sc.key_nruns[key];
             kb = sc.key_base[key];
         }
+        if (__ballot(len != 0u) == 0) continue;   // four empty keys
         if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * KLIST_CAP), len, kb, sub);
         for (int g = 0; g < 4; ++g) {
             const int64_t gk = k0 + g;
