@@ -52,7 +52,10 @@ def algorithmic_bytes_f32(dim: int, per_particle_q: bool):
         "rebin_tiles": 4,
         "rebin_scatter": 2 * s_rec,
         "deposit_bins_f32": s_dep,
-        "fused": 2 * s_push + 2 * s_rec + s_dep + 8,
+        "step_key_f32": s_push + 4,            # off, u read, key written
+        "step_group": 4 + 4,
+        "step_emit_f32": s_push + 4 + s_rec + q,
+        "fused": (s_push + 4) + 8 + (s_push + 4 + s_rec + q) + s_dep,
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
     }
 

@@ -2145,7 +2145,7 @@ template <int D, int SCHEME>
 __device__ __forceinline__ void cell_of(const DevTree &t, const DevInst &in, uint32_t rank, const float (&o)[D],
                                         uint32_t (&c)[D]) {
     const uint32_t S = (uint32_t)in.S;
-    unlinear<D>(ld_off(t.cell_tab, (uint32_t)in.ptab + rank), in.L, S, c);
+    unlinear<D>(ld_const(t.cell_tab, (uint32_t)in.ptab + rank), in.L, S, c);
     if (SCHEME == PIC_PIDT) {
         const uint32_t half = (S - 1u) >> 1;
 #pragma unroll
@@ -2221,11 +2221,40 @@ __device__ __forceinline__ uint32_t push_f32(const DevTree &t, const DevInst &in
         for (int k = 1; k < D; ++k) wc *= ((cc >> k) & 1) ? f[k] : g[k];
         w[cc] = wc;
     }
+    // corner field: scalar loads for the lanes sharing the first pending
+    // lane's cell (two passes), per-lane loads for the rest
+    float Ec[1 << D][D];
+    uint64_t pend = __ballot(1);
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        if (!pend) break;
+        const int l = __builtin_ctzll(pend);
+        const uint32_t v0u = (uint32_t)__builtin_amdgcn_readlane((int)vid[0], l);
+        const bool mine = vid[0] == v0u;
+        pend &= ~__ballot(mine);
+        uint32_t vu[1 << D];
+#pragma unroll
+        for (int cc = 0; cc < (1 << D); ++cc) vu[cc] = (uint32_t)__builtin_amdgcn_readlane((int)vid[cc], l);
+#pragma unroll
+        for (int cc = 0; cc < (1 << D); ++cc)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float eu = (float)ld_const(P.E[j], vu[cc]);
+                if (mine) Ec[cc][j] = eu;
+            }
+    }
+    if ((pend >> lane) & 1ull) {
+#pragma unroll
+        for (int cc = 0; cc < (1 << D); ++cc)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Ec[cc][j] = (float)ld_off(P.E[j], vid[cc]);
+    }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        float e = w[0] * (float)ld_off(P.E[j], vid[0]);
+        float e = w[0] * Ec[0][j];
 #pragma unroll
-        for (int cc = 1; cc < (1 << D); ++cc) e += w[cc] * (float)ld_off(P.E[j], vid[cc]);
+        for (int cc = 1; cc < (1 << D); ++cc) e += w[cc] * Ec[cc][j];
         const float uj = u[j] + kick * e;
         const float tp = f[j] + uj;
         float fl = floorf(tp);
@@ -2302,6 +2331,179 @@ __global__ __launch_bounds__(256) void k_gather_push_f32(DevTree t, DevInst in0,
         }
         bin_out[p] = nb;
         if (bad) flag_status(t.status, bad);
+    }
+}
+
+// Old bin of slot p with the wavefront's help: its slots are consecutive, so
+// the first pending lane's bin is found once (scalar loads) and the lanes in
+// it and in the next two bins are served from scalar loads of their bounds;
+// lanes left search on their own.
+__device__ __forceinline__ uint32_t old_bin_wave(const int64_t *start, uint32_t n_bins, const uint32_t *tile_bin,
+                                                 int tile, int64_t p) {
+    uint64_t pend = __ballot(1);
+    const uint32_t lane = __lane_id();
+    const int l = __builtin_ctzll(pend);
+    const int64_t pu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)p, l)) |
+                                 ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)p >> 32), l)
+                                  << 32));
+    uint32_t lo = 0, hi = n_bins - 1u;
+    if (tile_bin) {
+        const int64_t tl = pu / tile;
+        lo = min(ld_const(tile_bin, (uint32_t)(2 * tl)), n_bins - 1u);
+        hi = min(max(ld_const(tile_bin, (uint32_t)(2 * tl + 1)), lo + 1u), n_bins) - 1u;
+    }
+    while (lo < hi) {
+        const uint32_t m = (lo + hi + 1u) >> 1;
+        if (ld_const(start, m) <= pu) lo = m;
+        else hi = m - 1u;
+    }
+    uint32_t ob = 0, bu = lo;
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        if (!pend || bu >= n_bins) break;
+        const int64_t s0 = ld_const(start, bu), s1 = ld_const(start, bu + 1u);
+        const bool mine = ((pend >> lane) & 1ull) && s0 <= p && p < s1;
+        if (mine) ob = bu;
+        pend &= ~__ballot(mine);
+        ++bu;
+    }
+    if ((pend >> lane) & 1ull) ob = old_bin_of(start, n_bins, tile_bin, tile, p);
+    return ob;
+}
+
+// FP32 form, key pass of pic_step: one particle per thread, pushed, its key
+// 2*bin + arrived written out (a particle arrives iff its bin changes: the
+// bin is implicit in the segment it is stored in).  Clears the per-call
+// counters.
+template <int D, int SCHEME, bool MULTI>
+__global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
+                                                      double dt0, const double *qa, const double *da,
+                                                      const int64_t *inst_start, const int64_t *bin_start,
+                                                      uint32_t n_bins, const uint32_t *tile_bin, int tile,
+                                                      uint32_t *key_out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        int ii = 0;
+        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+        const DevInst &in = MULTI ? t.inst[ii] : in0;
+        const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+        const double dt = (MULTI && da) ? da[ii] : dt0;
+        const float kick = (float)(qmdt * dt * in.Sd);
+        uint32_t bad = 0;
+        float o[D], u[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            o[k] = P.off[k][p];
+            u[k] = P.u[k][p];
+        }
+        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, tile, p);
+        uint32_t c[D];
+        cell_of<D, SCHEME>(t, in, local_rank<SCHEME>(in, ob, bad), o, c);
+        uint32_t nb = push_f32<D, SCHEME>(t, in, P, c, o, u, kick, bad);
+        if (nb >= n_bins) bad |= PIC_DEV_RANGE;
+        nb = min(nb, n_bins - 1u);
+        key_out[p] = 2u * nb + (nb == ob ? 0u : 1u);
+        if (bad) flag_status(t.status, bad);
+    }
+}
+
+// FP32 form, emit pass of pic_step: the state pushed again is staged through
+// LDS in tile-sorted order, one column at a time, and written run by run (as
+// k_step_emit).
+template <int D, int SCHEME, bool MULTI, int TILE, int NT>
+__global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
+                                                      double dt0, const double *qa, const double *da,
+                                                      const int64_t *inst_start, const int64_t *bin_start,
+                                                      uint32_t n_bins, const uint32_t *tile_bin,
+                                                      const uint32_t *meta, const uint32_t *run_dest,
+                                                      const uint32_t *run_info, F32Ptrs out, Cols extra, int xcd) {
+    constexpr int IPT = TILE / NT;
+    __shared__ uint64_t s_val[TILE];
+    __shared__ uint32_t s_dst[TILE];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    const int cnt = (int)min((int64_t)TILE, n - lo);
+    for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
+    float o[IPT][D], u[IPT][D];
+    uint32_t mt[IPT], dst[IPT], q[IPT];
+    uint32_t bad = 0, miss = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        const bool ok = p < n;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            o[j][k] = ok ? P.off[k][p] : 0.0f;
+            u[j][k] = ok ? P.u[k][p] : 0.0f;
+        }
+        mt[j] = ok ? meta[p] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        dst[j] = ~0u;
+        q[j] = ~0u;
+        if (p < n) {
+            const uint32_t rid = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u), rank = mt[j] >> 16;
+            const uint32_t d = run_dest[lo + rid] + rank;
+            const uint32_t qq = (run_info[lo + rid] & 0xffffu) + rank;
+            if (d < (uint32_t)n && qq < (uint32_t)cnt && rid == (mt[j] & 0xffffu)) {
+                dst[j] = d;
+                q[j] = qq;
+            } else {
+                miss = 1;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = base + 64 * j;
+        if (p >= n) continue;
+        int ii = 0;
+        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+        const DevInst &in = MULTI ? t.inst[ii] : in0;
+        const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+        const double dt = (MULTI && da) ? da[ii] : dt0;
+        const float kick = (float)(qmdt * dt * in.Sd);
+        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, TILE, p);
+        uint32_t c[D];
+        cell_of<D, SCHEME>(t, in, local_rank<SCHEME>(in, ob, bad), o[j], c);
+        push_f32<D, SCHEME>(t, in, P, c, o[j], u[j], kick, bad);
+    }
+    if (miss) flag_status(t.status, PIC_DEV_RANGE);
+    __syncthreads();   // s_dst cleared
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+        if (dst[j] != ~0u) s_dst[q[j]] = dst[j];
+    const int ncol = 2 * D + extra.n;
+    for (int c = 0; c < ncol; ++c) {
+        const bool st = c < 2 * D;
+        const bool wide = !st && extra.bytes[c - 2 * D] == 8;
+        if (st) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u) s_val[q[j]] = __float_as_uint(c < D ? o[j][c] : u[j][c - D]);
+        } else {
+            const int e = c - 2 * D;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u)
+                    s_val[q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
+                                       : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
+        }
+        __syncthreads();
+        void *ob = st ? (void *)(c < D ? out.off[c] : out.u[c - D]) : extra.out[c - 2 * D];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int qq = tid + i * NT;
+            if (qq >= cnt) break;
+            const uint32_t d = s_dst[qq];
+            if (d == ~0u) continue;
+            if (wide) ((uint64_t *)ob)[d] = s_val[qq];
+            else ((uint32_t *)ob)[d] = (uint32_t)s_val[qq];
+        }
+        __syncthreads();
     }
 }
 
@@ -2948,6 +3150,25 @@ size_t step_f32_scratch_bytes(const pic_tree *t, int64_t n, int scheme) {
 // One FP32 step: gather + push in place on `in` (old bins from the tile
 // bounds of the old order), stable re-bin of the FP32 columns into `out`,
 // deposit on `out`.
+template <int D, int SCH, bool MULTI>
+static void step_passes_f32(const pic_tree *t, const F32Ptrs &P, const F32Ptrs &Q, int64_t n, double qmdt, double dt,
+                            const double *qa, const double *da, const int64_t *inst_start, const int64_t *old_start,
+                            uint32_t n_bins, const RebinScratch &sc, const Cols &extra, int64_t *new_start,
+                            hipStream_t s) {
+    constexpr int TILE = 2048;
+    const int64_t tiles = (n + TILE - 1) / TILE;
+    PIC_LAUNCH("step_key_f32", (k_step_key_f32<D, SCH, MULTI>), dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
+               t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
+               TILE, sc.keys);
+    PIC_LAUNCH("step_group", (k_step_group<8>), dim3(tiles), dim3(RB_THREADS), 0, s, (const uint32_t *)sc.keys, n, sc,
+               sc.meta, 0);
+    launch_step_middle(t, n, n_bins, sc, new_start, s);
+    PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024>), dim3(tiles), dim3(1024), 0, s, t->dt,
+               t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
+               (const uint32_t *)sc.meta, (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, Q, extra,
+               g_tune.xcd_tiles);
+}
+
 hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
                            const double *const *E, double qmdt, double dt, const pic_push_params *pp,
                            const Cols &extra, pic_particles *out, int64_t *new_start, int q_col, double q_uniform,
@@ -2955,6 +3176,23 @@ hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, con
     const int64_t n = in->n;
     const int64_t n_bins = n_bins_of(t, scheme);
     if (scratch_bytes < step_f32_scratch_bytes(t, n, scheme)) return hipErrorInvalidValue;
+    if (g_tune.step_rank != 0 && n > 0) {
+        // key, group, scan, place and emit passes, as the FP64 step
+        constexpr int TILE = 2048;
+        const RebinLayout L = rebin_layout(n, n_bins, TILE);
+        char *base = (char *)scratch;
+        const RebinScratch sc = bind_scratch(L, base);
+        const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
+        PIC_LAUNCH("rebin_prep", k_rebin_prep, dim3(grid_for(std::max(zero_words, n_bins), 256, 4096)), dim3(256), 0,
+                   s, (uint32_t *)(base + L.key_cnt), zero_words, old_start, n_bins, n, TILE, sc);
+        const F32Ptrs P = make_f32(t, in, E), Q = make_f32(t, out, E);
+        const double *qa = pp ? pp->qmdt_dev : nullptr;
+        const double *da = pp ? pp->dt_dev : nullptr;
+        PIC_SWITCH_DSM(step_passes_f32, t, P, Q, n, qmdt, dt, qa, da, in->inst_start_dev, old_start,
+                       (uint32_t)n_bins, sc, extra, new_start, s);
+        const double *q = q_col >= 0 ? (const double *)extra.out[q_col] : nullptr;
+        return launch_deposit_f32(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);
+    }
     const size_t rb = rebin_scratch_bytes(t, n, scheme);
     char *base = (char *)scratch;
     uint32_t *bins = (uint32_t *)(base + rb);
