@@ -442,6 +442,7 @@ struct RebinScratch {
     uint32_t *key_cnt;    // 2*n_bins (zeroed per call)
     uint32_t *key_nruns;  // 2*n_bins (zeroed per call)
     uint32_t *key_fill;   // 2*n_bins (zeroed per call)
+    uint64_t *key_cn;     // 2*n_bins (zeroed per call): fused step, count << 32 | runs per key
     uint32_t *key_base;   // 2*n_bins
     uint32_t *list_off;   // 2*n_bins + 1
     uint32_t *list;       // total runs <= n_tiles * TILE
@@ -885,8 +886,9 @@ __global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint3
         const uint64_t k = k0 + j;
         c[j] = r[j] = 0;
         if (k < n_keys) {
-            c[j] = sc.key_cnt[k];
-            r[j] = sc.key_nruns[k];
+            const uint64_t cn = sc.key_cn[k];
+            c[j] = (uint32_t)(cn >> 32);
+            r[j] = (uint32_t)cn;
         }
         cs += c[j];
         rs += r[j];
@@ -986,7 +988,7 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
         const int64_t key = k0 + grp;
         uint32_t len = 0, kb = 0;
         if (key < n_keys) {
-            len = sc.key_nruns[key];
+            len = (uint32_t)sc.key_cn[key];
             kb = sc.key_base[key];
         }
         if (__ballot(len != 0u) == 0) continue;   // four empty keys
@@ -1601,8 +1603,10 @@ __device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key
         const uint32_t k = k1[e] - 1u;
         sc.run_key[lo + ri] = k;
         sc.run_info[lo + ri] = lb | (tot[e] << 16);
-        atomicAdd(&sc.key_cnt[k], tot[e]);
-        const uint32_t pos = atomicAdd(&sc.key_nruns[k], 1u);
+        // one atomic per run: the key's particle count (high half) and its
+        // run count (low half), whose old value is the run's list position
+        const uint32_t pos = (uint32_t)atomicAdd((unsigned long long *)&sc.key_cn[k],
+                                                 ((unsigned long long)tot[e] << 32) | 1ull);
         const uint32_t a = (uint32_t)(lo + ri);
         if (pos < (uint32_t)KLIST_CAP) sc.klist[(int64_t)k * KLIST_CAP + pos] = a;
         else sc.knext[a] = atomicExch(&sc.khead[k], a + 1u);
@@ -1906,12 +1910,31 @@ __global__ void k_rebin_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_
 
 // Sum over groups of G consecutive lanes (butterfly inside the group, fixed
 // order, so the result is the same on every run).
+// A double moved across lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over groups of G consecutive lanes.  Inside a row of 16 lanes the
+// partners come by DPP (swap neighbours, swap pairs, mirror the half row,
+// mirror the row), across rows by lane shuffles.  Each step adds a lane's
+// value and its partner's, and a + b == b + a, so every lane of a group ends
+// with the same bits, and the tree is fixed: the result does not depend on
+// timing.
 template <int G, int N>
 __device__ __forceinline__ void group_sum(double (&acc)[N]) {
 #pragma unroll
-    for (int o = G >> 1; o > 0; o >>= 1)
-#pragma unroll
-        for (int c = 0; c < N; ++c) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], o, 64));
+    for (int c = 0; c < N; ++c) {
+        if (G >= 2) acc[c] = __dadd_rn(acc[c], dpp_f64<0xB1>(acc[c]));    // quad_perm [1,0,3,2]
+        if (G >= 4) acc[c] = __dadd_rn(acc[c], dpp_f64<0x4E>(acc[c]));    // quad_perm [2,3,0,1]
+        if (G >= 8) acc[c] = __dadd_rn(acc[c], dpp_f64<0x141>(acc[c]));   // row_half_mirror
+        if (G >= 16) acc[c] = __dadd_rn(acc[c], dpp_f64<0x140>(acc[c]));  // row_mirror
+        if (G >= 32) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], 16, 64));
+        if (G >= 64) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], 32, 64));
+    }
 }
 
 // Accumulate one particle's restriction weights: PIT per leaf corner, PIDT
@@ -1987,7 +2010,7 @@ __global__ __launch_bounds__(256) void k_deposit_bins(DevTree t, DevInst in0, F6
         double acc[NS];
 #pragma unroll
         for (int c = 0; c < NS; ++c) acc[c] = 0.0;
-        int64_t p0 = bin_start[b], p1 = bin_start[b + 1];
+        int64_t p0 = ld_const(bin_start, (uint32_t)b), p1 = ld_const(bin_start, (uint32_t)b + 1u);
         if (p0 < 0 || p1 > n || p0 > p1) {             // malformed offsets: flag, touch nothing
             if (lane == 0) flag_status(t.status, PIC_DEV_RANGE);
             p0 = p1 = 0;
@@ -2744,7 +2767,8 @@ static int64_t n_bins_of(const pic_tree *t, int scheme) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct RebinLayout {
-    size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_base, list_off,
+    size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_cn, key_base,
+        list_off,
         list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, total;
 };
 
@@ -2764,6 +2788,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.key_cnt = o; o = align256(o + keys * 4);      // key_cnt, key_nruns, key_fill, the scan state and
     L.key_nruns = o; o = align256(o + keys * 4);    // the block counter are contiguous: one fill clears
     L.key_fill = o; o = align256(o + keys * 4);     // them all
+    L.key_cn = o; o = align256(o + keys * 8);
     L.scan_state = o; o = align256(o + scan_blocks * 8);
     L.scan_ctr = o; o = align256(o + 4);
     L.khead = o; o = align256(o + keys * 4);
@@ -2827,6 +2852,7 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.tile_nruns = (uint32_t *)(base + L.tile_nruns);
     sc.key_cnt = (uint32_t *)(base + L.key_cnt);
     sc.key_nruns = (uint32_t *)(base + L.key_nruns);
+    sc.key_cn = (uint64_t *)(base + L.key_cn);
     sc.key_fill = (uint32_t *)(base + L.key_fill);
     sc.key_base = (uint32_t *)(base + L.key_base);
     sc.list_off = (uint32_t *)(base + L.list_off);
