@@ -345,6 +345,7 @@ pic_status pic_profile_only(const char *name);
  *   "scatter_nt"    1 = non-temporal stores for the re-binned records (default 0);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
+ *   "deposit_bpw"   bins such a lane group takes one after the other, 1 or 2 (default 1);
  *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048);
  *   "step_rank"     pic_step's passes: 1 = the first pass ranks every particle inside
  *                   its tile and the second only pushes and writes, 2 = as 1 with the

@@ -555,6 +555,9 @@ pic_status pic_tune_set(const char *name, int64_t value) {
     } else if (k == "emit_stage") {
         if (value < 0 || value > 2) return PIC_E_ARG;
         g_tune.emit_stage = (int)value;
+    } else if (k == "deposit_bpw") {
+        if (value != 1 && value != 2) return PIC_E_ARG;
+        g_tune.deposit_bpw = (int)value;
     } else if (k == "emit_threads") {
         if (value != 256 && value != 512 && value != 1024) return PIC_E_ARG;
         g_tune.emit_threads = (int)value;
@@ -579,6 +582,7 @@ int64_t pic_tune_get(const char *name) {
     if (k == "xcd_tiles") return g_tune.xcd_tiles;
     if (k == "emit_stage") return g_tune.emit_stage;
     if (k == "emit_threads") return g_tune.emit_threads;
+    if (k == "deposit_bpw") return g_tune.deposit_bpw;
     return -1;
 }
 

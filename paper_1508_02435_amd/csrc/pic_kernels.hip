@@ -1946,13 +1946,24 @@ __device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp,
     Axis ax[D];
     uint32_t a[D];
     double f[D], g[D];
+    if (REG && SCHEME == PIC_PIT) {
+        // the stored positions lie in [0,1), so the cell is floor(y) and
+        // f = y - floor(y) is y - I exactly, without the integer cell
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
-        const uint32_t I = ax[k].T >> 1;
-        a[k] = REG ? I : div_pow3(I, e);
-        f[k] = REG ? __dsub_rn(ax[k].y, (double)I) : __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
-        g[k] = __dsub_rn(1.0, f[k]);
+        for (int k = 0; k < D; ++k) {
+            const double y = __dmul_rn(xp[k], in.Sd);
+            f[k] = __dsub_rn(y, floor(y));
+            g[k] = __dsub_rn(1.0, f[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
+            const uint32_t I = ax[k].T >> 1;
+            a[k] = REG ? I : div_pow3(I, e);
+            f[k] = REG ? __dsub_rn(ax[k].y, (double)I) : __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
+            g[k] = __dsub_rn(1.0, f[k]);
+        }
     }
     if (SCHEME == PIC_PIT) {
 #pragma unroll
@@ -1992,48 +2003,104 @@ __device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp,
 // arrive.  With per-particle charges the terms are q_p w_c, otherwise w_c
 // (the uniform charge is applied per vertex).
 template <int D, int SCHEME, bool REG, int G, int K>
-__global__ __launch_bounds__(256) void k_deposit_bins(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
-                                                      const int64_t *bin_start, int64_t n_bins, const double *q,
-                                                      double *partial) {
-    constexpr int NS = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
-    const int lane = threadIdx.x & (G - 1);
-    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
-    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / G) + (threadIdx.x / G); b < n_bins; b += groups) {
+struct DepositBin {
+    static constexpr int NS = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
+    const DevInst *in;
+    int e;
+    double s, rinv;
+    uint32_t su;
+    int64_t p0, p1;
+
+    __device__ __forceinline__ void setup(const DevTree &t, const DevInst &in0, const int64_t *bin_start, int64_t n,
+                                          int64_t b, int lane) {
         int ii = 0;
         if (t.n_inst > 1) ii = SCHEME == PIC_PIT ? t.leaf_inst[b] : t.pidt_inst[b];
-        const DevInst &in = t.n_inst > 1 ? t.inst[ii] : in0;
-        const int lev = REG ? in.L : (SCHEME == PIC_PIT ? t.leaf_level[b] : t.pidt_level[b]);
-        const int e = in.L - lev;
-        const double s = (double)pow3_u32(e);
-        const uint32_t su = pow3_u32(e);
-        const double rinv = in.rinv[lev];
-        double acc[NS];
-#pragma unroll
-        for (int c = 0; c < NS; ++c) acc[c] = 0.0;
-        int64_t p0 = ld_const(bin_start, (uint32_t)b), p1 = ld_const(bin_start, (uint32_t)b + 1u);
+        in = t.n_inst > 1 ? &t.inst[ii] : &in0;
+        const int lev = REG ? in->L : (SCHEME == PIC_PIT ? t.leaf_level[b] : t.pidt_level[b]);
+        e = in->L - lev;
+        s = (double)pow3_u32(e);
+        su = pow3_u32(e);
+        rinv = in->rinv[lev];
+        p0 = ld_const(bin_start, (uint32_t)b);
+        p1 = ld_const(bin_start, (uint32_t)b + 1u);
         if (p0 < 0 || p1 > n || p0 > p1) {             // malformed offsets: flag, touch nothing
             if (lane == 0) flag_status(t.status, PIC_DEV_RANGE);
             p0 = p1 = 0;
         }
-        for (int64_t base = p0; base < p1; base += G * K) {
-            double xs[K][D], qs[K];
+    }
+    // one batch of G*K particles from `base`: loads, then weights
+    __device__ __forceinline__ void load(const F64Ptrs &P, const double *q, int64_t base, int lane, double (&xs)[K][D],
+                                         double (&qs)[K]) const {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int64_t p = base + lane + G * k;
-                const bool ok = p < p1;
+        for (int k = 0; k < K; ++k) {
+            const int64_t p = base + lane + G * k;
+            const bool ok = p < p1;
 #pragma unroll
-                for (int d = 0; d < D; ++d) xs[k][d] = ok ? P.x[d][p] : 0.0;
-                qs[k] = (ok && q) ? q[p] : 1.0;
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (base + lane + G * k < p1)
-                    deposit_one<D, SCHEME, REG, NS>(in, xs[k], e, s, su, rinv, qs[k], q != nullptr, acc);
+            for (int d = 0; d < D; ++d) xs[k][d] = ok ? P.x[d][p] : 0.0;
+            qs[k] = (ok && q) ? q[p] : 1.0;
         }
-        group_sum<G, NS>(acc);
-        if (lane == 0) {
+    }
+    __device__ __forceinline__ void add(const double (&xs)[K][D], const double (&qs)[K], const double *q, int64_t base,
+                                        int lane, double (&acc)[NS]) const {
 #pragma unroll
-            for (int c = 0; c < NS; ++c) partial[b * NS + c] = acc[c];
+        for (int k = 0; k < K; ++k)
+            if (base + lane + G * k < p1)
+                deposit_one<D, SCHEME, REG, NS>(*in, xs[k], e, s, su, rinv, qs[k], q != nullptr, acc);
+    }
+};
+
+// G lanes per bin (64/G bins per wavefront), BPW bins per group one after
+// the other.  A bin's particles are taken in batches of G*K; when the group's
+// bins each fit one batch, every load of all of them is issued before the
+// first is used, so the group waits for memory once.  With per-particle
+// charges the terms are q_p w_c, otherwise w_c (the uniform charge is applied
+// per vertex).
+template <int D, int SCHEME, bool REG, int G, int K, int BPW>
+__global__ __launch_bounds__(256) void k_deposit_bins(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                      const int64_t *bin_start, int64_t n_bins, const double *q,
+                                                      double *partial) {
+    using DB = DepositBin<D, SCHEME, REG, G, K>;
+    constexpr int NS = DB::NS;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
+    const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x / G) + (threadIdx.x / G);
+    for (int64_t b0 = g0 * BPW; b0 < n_bins; b0 += groups * BPW) {
+        DB bin[BPW];
+        bool one_batch = true;
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const int64_t b = min(b0 + i, n_bins - 1);
+            bin[i].setup(t, in0, bin_start, n, b, lane);
+            if (b0 + i >= n_bins) bin[i].p1 = bin[i].p0;   // past the end: empty
+            one_batch &= bin[i].p1 - bin[i].p0 <= (int64_t)G * K;
+        }
+        double acc[BPW][NS];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) acc[i][c] = 0.0;
+        if (one_batch) {
+            double xs[BPW][K][D], qs[BPW][K];
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) bin[i].load(P, q, bin[i].p0, lane, xs[i], qs[i]);
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) bin[i].add(xs[i], qs[i], q, bin[i].p0, lane, acc[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < BPW; ++i)
+                for (int64_t base = bin[i].p0; base < bin[i].p1; base += G * K) {
+                    double xs[K][D], qs[K];
+                    bin[i].load(P, q, base, lane, xs, qs);
+                    bin[i].add(xs, qs, q, base, lane, acc[i]);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            group_sum<G, NS>(acc[i]);
+            if (lane == 0 && b0 + i < n_bins) {
+#pragma unroll
+                for (int c = 0; c < NS; ++c) partial[(b0 + i) * NS + c] = acc[i][c];
+            }
         }
     }
 }
@@ -3051,8 +3118,16 @@ size_t deposit_scratch_bytes(const pic_tree *t, int scheme) {
 }
 
 #define PIC_DEP_BINS(D, SCH, REG, G)                                                                          \
-    PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 256 / G>), dim3(grid_for(n_bins, 256 / G, 1 << 18)), \
-               dim3(256), 0, s, t->dt, t->inst0, P, p->n, bin_start, n_bins, q, partial)
+    do {                                                                                                      \
+        if (g_tune.deposit_bpw == 2)                                                                          \
+            PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 256 / G, 2>),                          \
+                       dim3(grid_for((n_bins + 1) / 2, 256 / G, 1 << 18)), dim3(256), 0, s, t->dt, t->inst0, P, p->n, \
+                       bin_start, n_bins, q, partial);                                                        \
+        else                                                                                                  \
+            PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 256 / G, 1>),                          \
+                       dim3(grid_for(n_bins, 256 / G, 1 << 18)), dim3(256), 0, s, t->dt, t->inst0, P, p->n,   \
+                       bin_start, n_bins, q, partial);                                                        \
+    } while (0)
 
 #define PIC_DISPATCH_DEP(D, SCH, REG)                                                                         \
     do {                                                                                                     \
