@@ -3,7 +3,7 @@
  *
  * One time step of the particle side of a particle-in-cell (PIC) cycle on a
  * k = 3 spacetree (paper "Two Particle-in-Grid Realisations on Spacetrees",
- * Sec. 2 for the cycle, Sec. 3 for the tree, Sec. 4 for the particle
+ * Sec. 3 for the cycle, Sec. 4 for the tree, Sec. 5 for the particle
  * stores), split into three calls that run on one GPU stream:
  *
  *   pic_gather_push  field gather E_i = R^T(x_i) E and leapfrog push, and the
@@ -56,7 +56,7 @@ typedef int32_t pic_status;
 #define PIC_E_RANGE 7      /* device: a position lay outside [0,1), or a bin outside the tree */
 #define PIC_E_STATE 8      /* call order violated (e.g. tree not uploaded) */
 
-/* Particle storage schemes (paper Sec. 4.1 and Sec. 4.2). */
+/* Particle storage schemes (paper Sec. 5.1 and Sec. 5.2). */
 #define PIC_PIT 0          /* particle in tree: bin = leaf covering x (Theorem 1) */
 #define PIC_PIDT 1         /* particle in dual tree: bin = vertex of that leaf whose
                               dual cell covers x (Theorem 2) */
@@ -71,8 +71,8 @@ typedef struct pic_tree pic_tree;   /* opaque host object */
 
 /*
  * Build the host description of a forest of `n_inst` spacetrees of the same
- * dimension over the periodic unit box (paper Sec. 3: root = unit box, a
- * refined cell has 3^d children, leaves are unrefined cells; Sec. 3.2 dual
+ * dimension over the periodic unit box (paper Sec. 4: root = unit box, a
+ * refined cell has 3^d children, leaves are unrefined cells; Sec. 4.1 dual
  * grid).  A single tree is a forest of one.
  *
  *   dim        2 or 3.
@@ -194,7 +194,7 @@ pic_status pic_locate(const pic_tree *tree, int32_t scheme, int32_t precision,
                       uint32_t *bin_dev, void *stream);
 
 /*
- * Gather + push (paper Sec. 2 items 3 and 4; d-linear shape functions).
+ * Gather + push (paper Sec. 3 steps 3 and 4; d-linear shape functions).
  * For every particle, in place:
  *   E_p = sum_c w_c(x) E[vtx_c]   over the 2^d corners of the leaf holding x,
  *   v  <- v + qmdt * E_p,  x <- x + v * dt,  x <- x - floor(x) (1.0 -> 0.0),
@@ -228,7 +228,7 @@ pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precisi
 size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_t precision);
 
 /*
- * Re-bin (paper Sec. 4: after the move every particle is held by the grid
+ * Re-bin (paper Sec. 5: after the move every particle is held by the grid
  * entity covering it; Theorems 1 and 2; "bucket sort" into children).
  * Output order: bins ascending; inside a bin first the particles that were
  * already in it (in their old order), then the ones that arrived (in their
@@ -248,7 +248,7 @@ pic_status pic_rebin(const pic_tree *tree, int32_t scheme, int64_t n,
                      void *scratch_dev, size_t scratch_bytes, void *stream);
 
 /*
- * Deposit (paper Sec. 2 item 1): rho_v = sum_p q_p w_v(x_p) for a sorted set
+ * Deposit (paper Sec. 3 step 1): rho_v = sum_p q_p w_v(x_p) for a sorted set
  * (bin_start_dev from pic_rebin for the same scheme).  rho_dev receives
  * n_vertices doubles (vertex charge, overwritten).  q_dev: per-particle
  * charge (n doubles) or NULL for q_uniform.  No floating-point atomics: each
@@ -262,13 +262,16 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
 
 /*
  * One whole step in a single call: the same result as pic_gather_push, then
- * pic_rebin (in -> out) and pic_deposit (on out) (paper Sec. 2 items 1, 3, 4;
- * Sec. 4 re-binning).  FP64 form: two passes over `in`, which stays
- * unchanged: the first pushes each tile of particles and counts its particles
- * per (new bin, arrived); after a scan over the counts the second pushes the
- * tile again (same arithmetic, same bins) and writes every particle straight
- * to its final slot.  FP32 form: gather + push in place on `in` (whose
- * off/u then hold the pushed values in the old order), then the re-bin.
+ * pic_rebin (in -> out) and pic_deposit (on out) (paper Sec. 3 steps 1, 3, 4;
+ * Sec. 5 re-binning).  `in` stays unchanged (both forms, unless the knob
+ * "step_rank" is 0, where the FP32 form pushes `in` in place first): a key
+ * pass pushes every particle and writes its key 2 * new bin + arrived; a
+ * group pass ranks every particle among the particles of its tile with the
+ * same key, in tile order; a scan and a placement give every run (tile, key)
+ * its destination; an emit pass pushes each particle again (the same
+ * arithmetic, so the same state and bin) and writes it to its run's
+ * destination plus its rank, in tile-sorted order through LDS.  Then the
+ * deposit on `out`.
  *   in                 sorted set with offsets bin_start_dev.
  *   extra_in/out       n_extra further columns (4 or 8 bytes) carried along.
  *   q_column           index of the per-particle charge among the extra
@@ -304,7 +307,7 @@ pic_status pic_convert(const pic_tree *tree, int32_t scheme, int32_t to_precisio
 /* ------------------------------------------------------- measurement aids */
 
 /*
- * Stream benchmark of the paper's evaluation (Sec. 5, stream-like particle
+ * Stream benchmark of the paper's evaluation (Sec. 6.2, stream-like particle
  * throughput): every particle moves by one explicit Euler step x <- x + v dt
  * and is reflected at the walls of the unit box (x -> -x below 0, 2 - x
  * above 1, with v negated), with no grid.  x_dev, v_dev: dim pointers to n

@@ -8,11 +8,11 @@ adds the FP64 support pieces that sit outside the hot path (periodic Poisson
 solve and the vertex field), which the physics pins need.
 
 Paper sections followed (see the C file header for the readings):
-  Sec. 2   PIC cycle: deposit rho = sum R(x_i), solve, E = -grad V,
+  Sec. 3   PIC cycle: deposit rho = sum R(x_i), solve, E = -grad V,
            gather E_i = R^T(x_i) E, push.
-  Sec. 3   k=3 spacetree, dual grid, Peano ordering of the storage.
-  Sec. 4.1 PIT: each particle held by the leaf covering it (Theorem 1).
-  Sec. 4.2 PIDT: each particle held by the vertex whose dual cell covers it
+  Sec. 4   k=3 spacetree, dual grid, Peano ordering of the storage.
+  Sec. 5.1 PIT: each particle held by the leaf covering it (Theorem 1).
+  Sec. 5.2 PIDT: each particle held by the vertex whose dual cell covers it
            (Theorem 2).
   App. A   Langmuir-wave units and the Bohm-Gross relation.
 """

@@ -7,15 +7,15 @@
  * from the refinement masks it is given.
  *
  * What it computes (paper: "Two Particle-in-Grid Realisations on Spacetrees"):
- *   - the k=3 spacetree over the periodic unit box (Sec. 3): root, children
+ *   - the k=3 spacetree over the periodic unit box (Sec. 4): root, children
  *     by three cuts per axis, leaves = unrefined cells;
  *   - cell ownership: a particle belongs to the leaf that covers its position
- *     (PIT, Sec. 4.1, Theorem 1) or to the vertex of that leaf whose dual cell
- *     covers it (PIDT, Sec. 3 "Storing particles", Sec. 4.2, Theorem 2);
- *   - bins ordered along the Peano space-filling curve (Sec. 3 storage remark);
- *   - d-linear restriction R and its transpose (Sec. 2 items 1 and 3, and the
+ *     (PIT, Sec. 5.1, Theorem 1) or to the vertex of that leaf whose dual cell
+ *     covers it (PIDT, Sec. 4.2 "Storing particles", Sec. 5.2, Theorem 2);
+ *   - bins ordered along the Peano space-filling curve (Sec. 4.2 storage remark);
+ *   - d-linear restriction R and its transpose (Sec. 3 steps 1 and 3, and the
  *     d-linear shape-function remark): rho = sum_i R(x_i), E_i = R^T(x_i) E;
- *   - the push dv/dt = (q/m) E, dx/dt = v (Sec. 2 item 4) as leapfrog.
+ *   - the push dv/dt = (q/m) E, dx/dt = v (Sec. 3 step 4) as leapfrog.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - a particle's cell coordinate is y = fl(x * 3^L) (one rounding); cells

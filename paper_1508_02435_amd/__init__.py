@@ -5,8 +5,8 @@ for the C ABI).  This module only marshals arguments: PyTorch provides device
 memory and the current HIP stream.  There is no CPU fallback; if the library
 or a GPU is missing the calls raise.
 
-Paper: "Two Particle-in-Grid Realisations on Spacetrees" (Sec. 2 PIC cycle,
-Sec. 3 spacetree and dual grid, Sec. 4.1 PIT, Sec. 4.2 PIDT).
+Paper: "Two Particle-in-Grid Realisations on Spacetrees" (Sec. 3 PIC cycle,
+Sec. 4 spacetree and dual grid, Sec. 5.1 PIT, Sec. 5.2 PIDT).
 """
 from __future__ import annotations
 

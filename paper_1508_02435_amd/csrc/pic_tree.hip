@@ -1,16 +1,16 @@
 // pic_tree.hip -- host construction of the linearised spacetree forest.
 //
-// A k = 3 spacetree (paper Sec. 3) is stored as flat arrays:
+// A k = 3 spacetree (paper Sec. 4) is stored as flat arrays:
 //  * a level-major descent table: each refined, non-uniform node points at its
 //    3^d children (lexicographic child slots, so a child is found by index
 //    arithmetic); a node whose leaves all sit on one level ("uniform subtree",
 //    a regular tree's root being the extreme case) ends the descent and its
 //    leaves are ranked arithmetically by the Peano rank of their coordinates;
-//  * leaves ranked by their Peano key (the storage order of Sec. 3), with
+//  * leaves ranked by their Peano key (the storage order of Sec. 4.2), with
 //    their level, corner vertices and corner dual cells;
 //  * vertices = distinct leaf-corner positions (hanging ones included),
 //    numbered lexicographically per instance;
-//  * dual-grid bins (PIDT, Sec. 3.2 and 4.2) = (level, vertex of a leaf of that
+//  * dual-grid bins (PIDT, Sec. 4.1 and 5.2) = (level, vertex of a leaf of that
 //    level), keyed on the half-cell-shifted lattice on which dual cells nest
 //    for odd k.
 #include <algorithm>

@@ -27,7 +27,7 @@ def _lattice(dim, n):
 
 
 # ---------------------------------------------------------------------------
-# Peano index (paper Sec. 3, Peano ordering of cells and of their arrays)
+# Peano index (paper Sec. 4.2, Peano ordering of cells and of their arrays)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dim,L", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
@@ -61,7 +61,7 @@ def test_peano_matches_textbook_level1_order():
 
 
 # ---------------------------------------------------------------------------
-# Spacetree tables (paper Sec. 3)
+# Spacetree tables (paper Sec. 4)
 # ---------------------------------------------------------------------------
 
 def _geometric_leaves(spec):
@@ -211,7 +211,7 @@ def test_locate_rejects_positions_outside_the_box():
 
 
 # ---------------------------------------------------------------------------
-# d-linear restriction and its transpose (paper Sec. 2, items 1 and 3)
+# d-linear restriction and its transpose (paper Sec. 3, steps 1 and 3)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("spec", [W.regular_tree(2, 3), W.disc_tree(2, 2, 4), W.disc_tree(3, 1, 3)])
@@ -299,7 +299,7 @@ def test_deposit_conserves_charge(name):
 
 
 # ---------------------------------------------------------------------------
-# Push (paper Sec. 2 item 4): leapfrog, periodic wrap
+# Push (paper Sec. 3 step 4): leapfrog, periodic wrap
 # ---------------------------------------------------------------------------
 
 def test_free_streaming_matches_closed_form():
@@ -509,7 +509,7 @@ def test_fig16_ring_is_bohm_gross():
 
 @pytest.mark.parametrize("dim,L", [(2, 2), (2, 3), (3, 2)])
 def test_dual_cells_nest_along_the_curve(dim, L):
-    """Dual-grid consistency for odd k (Sec. 3, dual spacetree grid).
+    """Dual-grid consistency for odd k (Sec. 4.1, dual spacetree grid).
 
     The level-L vertices inside the dual cell of one level-(L-1) vertex B
     (that is b = 3B + {-1,0,1}^d) must occupy 3^d consecutive PIDT ranks.
