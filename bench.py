@@ -371,12 +371,16 @@ def main():
     # timed region: events only around the dominant kernel
     lib.pic_profile_only(dominant.encode())
     kernel_times(lib)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
         step(E, qmdt, dt, q_uniform=wl.q_uniform)
+    ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gpu_ms_step = ev0.elapsed_time(ev1) / args.steps
     launches, total = kernel_times(lib)[dominant]
     lib.pic_profile_only(None)
     lib.pic_profile_enable(0)
@@ -431,6 +435,8 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "particle updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        # stream time of the same timed steps (first launch to last completion), beside the wall clock
+        "gpu_ms_per_step": round(gpu_ms_step, 4),
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config].format(n=wl.n, leaves=int(tree.n_leaves)) +
                                f", {args.scheme.upper()}, {'FP32 offsets' if f32 else 'FP64'}, {args.path} path",

@@ -359,7 +359,7 @@ pic_status pic_profile_only(const char *name);
  *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
  *   "emit_stage"    the writing pass of pic_step stages 1 or 2 columns at a time
  *                   through LDS in tile-sorted order, or 0 = stores straight from
- *                   registers (default 1);
+ *                   registers (default 2);
  *   "emit_threads"  threads per block of that pass, 256, 512 or 1024 (default 1024);
  *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
  *                   regular instances (up to 2^21 cells per level), which the

@@ -106,7 +106,7 @@ struct Tuning {
     int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
     int step_rank = 2;      // fused step: 2 = key + group + emit, 1 = rank + emit, 0 = count + move
     int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
-    int emit_stage = 1;     // emit pass: columns staged through LDS per barrier (1 or 2), 0 = direct stores
+    int emit_stage = 2;     // emit pass: columns staged through LDS per barrier (1 or 2), 0 = direct stores
     int emit_threads = 1024; // threads per emit block: 256, 512 or 1024
     int deposit_bpw = 1;    // bins a deposit lane group takes one after the other: 1 or 2
     int regular_tables = 1; // build Peano rank tables for regular instances of trees created afterwards

@@ -1504,6 +1504,10 @@ struct RankShape {
     static_assert(H == TILE, "table size");
 };
 
+// Entries at the head of a tile's run table that the emit pass loads with
+// the tile's state (most tiles have fewer runs).
+constexpr int RUN_HEAD = 256;
+
 // Block b's tile when the tiles are spread over the chip's 8 XCDs in
 // contiguous chunks (consecutive blocks go to consecutive XCDs), so that the
 // tiles an XCD runs at the same time are neighbours and share its L2.
@@ -1515,7 +1519,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int on) {
 
 // LDS of the tile ranking.
 template <int IPT>
-struct RankSmem {
+struct alignas(16) RankSmem {
     uint32_t key[RankShape<IPT>::H];            // key + 1 (0: empty); run index after compaction
     uint16_t wc[4][RankShape<IPT>::H];          // per wavefront count of each slot, then its offset
     uint8_t tag[4][RankShape<IPT>::H];          // per wavefront representative lane of each slot
@@ -1523,14 +1527,43 @@ struct RankSmem {
     uint32_t wsum[4];
 };
 
+// W consecutive 32-bit LDS words (16-byte aligned for W >= 4, 8-byte for W
+// == 2) moved in 16- or 8-byte accesses.
+template <int W>
+__device__ __forceinline__ void lds_load_words(uint32_t (&r)[W], const uint32_t *p) {
+    if constexpr (W % 4 == 0) {
+#pragma unroll
+        for (int c = 0; c < W / 4; ++c) {
+            const uint4 v = ((const uint4 *)p)[c];
+            r[4 * c] = v.x; r[4 * c + 1] = v.y; r[4 * c + 2] = v.z; r[4 * c + 3] = v.w;
+        }
+    } else {
+        static_assert(W == 2, "word count");
+        const uint2 v = *(const uint2 *)p;
+        r[0] = v.x; r[1] = v.y;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void lds_store_words(uint32_t *p, const uint32_t (&r)[W]) {
+    if constexpr (W % 4 == 0) {
+#pragma unroll
+        for (int c = 0; c < W / 4; ++c) ((uint4 *)p)[c] = make_uint4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]);
+    } else {
+        static_assert(W == 2, "word count");
+        *(uint2 *)p = make_uint2(r[0], r[1]);
+    }
+}
+
 template <int IPT>
 __device__ __forceinline__ void rank_clear(RankSmem<IPT> &S) {
+    // the key table and the per-wavefront counts are adjacent: one span of
+    // 16-byte stores
+    static_assert(offsetof(RankSmem<IPT>, wc) == sizeof(S.key), "layout");
+    constexpr int N16 = (int)(sizeof(S.key) + sizeof(S.wc)) / 16;
     const int tid = threadIdx.x;
-    for (int i = tid; i < RankShape<IPT>::H; i += RB_THREADS) {
-        S.key[i] = 0u;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S.wc[v][i] = 0;
-    }
+    uint4 *p = (uint4 *)&S.key[0];
+    for (int i = tid; i < N16; i += RB_THREADS) p[i] = make_uint4(0u, 0u, 0u, 0u);
     S.msk[tid >> 6][tid & 63] = 0ull;
 }
 
@@ -1578,41 +1611,54 @@ __device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key
     // compaction in slot order (a block scan): run index and tile-local
     // start of every occupied slot; the per-wave counts become per-wave
     // offsets (counts of the earlier wavefronts)
+    // (a thread's IPT slots are consecutive: their keys and counts move in
+    // wide LDS accesses)
     uint32_t k1[IPT], tot[IPT], packed = 0;
+    uint32_t cw[4][IPT / 2];
+    lds_load_words<IPT>(k1, &S.key[tid * IPT]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lds_load_words<IPT / 2>(cw[v], (const uint32_t *)&S.wc[v][tid * IPT]);
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const int i = tid * IPT + e;
-        k1[e] = S.key[i];
         tot[e] = 0;
-        if (k1[e]) {
+        const int sh = 16 * (e & 1);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const uint32_t c = S.wc[v][i];
-                S.wc[v][i] = (uint16_t)tot[e];
-                tot[e] += c;
-            }
-            packed += 1u + (tot[e] << 16);
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t c = (cw[v][e >> 1] >> sh) & 0xffffu;
+            cw[v][e >> 1] = (cw[v][e >> 1] & ~(0xffffu << sh)) | (tot[e] << sh);
+            tot[e] += c;
         }
+        if (k1[e]) packed += 1u + (tot[e] << 16);
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lds_store_words<IPT / 2>((uint32_t *)&S.wc[v][tid * IPT], cw[v]);
     uint32_t total;
     const uint32_t ex = block_excl_scan(packed, S.wsum, &total);
     uint32_t ri = ex & 0xffffu, lb = ex >> 16;
+    uint32_t pos[IPT], rr[IPT];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
+        pos[e] = 0u;
+        rr[e] = ri;
         if (!k1[e]) continue;
         const uint32_t k = k1[e] - 1u;
         sc.run_key[lo + ri] = k;
         sc.run_info[lo + ri] = lb | (tot[e] << 16);
         // one atomic per run: the key's particle count (high half) and its
-        // run count (low half), whose old value is the run's list position
-        const uint32_t pos = (uint32_t)atomicAdd((unsigned long long *)&sc.key_cn[k],
-                                                 ((unsigned long long)tot[e] << 32) | 1ull);
-        const uint32_t a = (uint32_t)(lo + ri);
-        if (pos < (uint32_t)KLIST_CAP) sc.klist[(int64_t)k * KLIST_CAP + pos] = a;
-        else sc.knext[a] = atomicExch(&sc.khead[k], a + 1u);
-        S.key[tid * IPT + e] = ri;
+        // run count (low half), whose old value is the run's list position;
+        // a thread's atomics are all in flight before the first is used
+        pos[e] = (uint32_t)atomicAdd((unsigned long long *)&sc.key_cn[k],
+                                     ((unsigned long long)tot[e] << 32) | 1ull);
         ++ri;
         lb += tot[e];
+    }
+    lds_store_words<IPT>(&S.key[tid * IPT], rr);   // slot -> run index
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        if (!k1[e]) continue;
+        const uint32_t k = k1[e] - 1u, a = (uint32_t)lo + rr[e];
+        if (pos[e] < (uint32_t)KLIST_CAP) sc.klist[(int64_t)k * KLIST_CAP + pos[e]] = a;
+        else sc.knext[a] = atomicExch(&sc.khead[k], a + 1u);
     }
     __syncthreads();
     if (tid == 0) sc.tile_nruns[tile] = total & 0xffffu;
@@ -1694,7 +1740,6 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
         bool stay = false, known = !old_start;
         if (SCHEME == PIC_PIT && REG && !MULTI && old_start) {
             uint64_t pend = __ballot(1);
-            const uint32_t lane = __lane_id();
 #pragma unroll
             for (int it = 0; it < 2; ++it) {
                 if (!pend) break;
@@ -1708,7 +1753,6 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
                     known = true;
                 }
             }
-            (void)lane;
         }
         if (!known) stay = old_start[b] <= p && p < old_start[b + 1];
         key_out[p] = 2u * b + (stay ? 0u : 1u);
@@ -1753,6 +1797,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
     __shared__ uint64_t s_val[STAGE ? NS : 1][STAGE ? TILE : 1];
     __shared__ uint32_t s_dst[STAGE ? TILE : 1];
+    __shared__ uint32_t s_rd[RUN_HEAD], s_ro[RUN_HEAD];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
     const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
@@ -1764,6 +1809,13 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     uint32_t mt[IPT], dst[IPT], q[IPT];
     uint32_t bad = 0;
     const bool full = lo + TILE <= n;
+    // the head of the tile's run table (in range: the table has TILE entries
+    // per tile), loaded with the state rather than after the run indices
+    uint32_t rd0 = 0u, ro0 = 0u;
+    if (tid < RUN_HEAD) {
+        rd0 = run_dest[lo + tid];
+        ro0 = run_info[lo + tid];
+    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
@@ -1775,6 +1827,11 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         }
         mt[j] = ok ? meta[p] : 0u;
     }
+    if (tid < RUN_HEAD) {
+        s_rd[tid] = rd0;
+        s_ro[tid] = ro0 & 0xffffu;
+    }
+    __syncthreads();   // run head in LDS, s_dst cleared
     uint32_t miss = 0;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -1783,10 +1840,11 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         q[j] = ~0u;
         if (full || p < n) {
             const uint32_t rid = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u), rank = mt[j] >> 16;
-            const uint32_t d = run_dest[lo + rid] + rank;
+            const bool head = rid < (uint32_t)RUN_HEAD;
+            const uint32_t d = (head ? s_rd[rid] : run_dest[lo + rid]) + rank;
             dst[j] = (d < (uint32_t)n && rid == (mt[j] & 0xffffu)) ? d : ~0u;
             if (STAGE) {
-                const uint32_t qq = (run_info[lo + rid] & 0xffffu) + rank;
+                const uint32_t qq = (head ? s_ro[rid] : (run_info[lo + rid] & 0xffffu)) + rank;
                 q[j] = qq < (uint32_t)cnt ? qq : ~0u;
                 if (q[j] == ~0u) dst[j] = ~0u;
             }
@@ -1838,7 +1896,6 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         }
         return;
     }
-    __syncthreads();   // s_dst cleared
 #pragma unroll
     for (int j = 0; j < IPT; ++j)
         if (dst[j] != ~0u) s_dst[q[j]] = dst[j];
@@ -2510,6 +2567,7 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
     constexpr int IPT = TILE / NT;
     __shared__ uint64_t s_val[TILE];
     __shared__ uint32_t s_dst[TILE];
+    __shared__ uint32_t s_rd[RUN_HEAD], s_ro[RUN_HEAD];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
     const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
@@ -2518,6 +2576,11 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
     float o[IPT][D], u[IPT][D];
     uint32_t mt[IPT], dst[IPT], q[IPT];
     uint32_t bad = 0, miss = 0;
+    uint32_t rd0 = 0u, ro0 = 0u;
+    if (tid < RUN_HEAD) {
+        rd0 = run_dest[lo + tid];
+        ro0 = run_info[lo + tid];
+    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
@@ -2529,6 +2592,11 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
         }
         mt[j] = ok ? meta[p] : 0u;
     }
+    if (tid < RUN_HEAD) {
+        s_rd[tid] = rd0;
+        s_ro[tid] = ro0 & 0xffffu;
+    }
+    __syncthreads();   // run head in LDS, s_dst cleared
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
@@ -2536,8 +2604,9 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
         q[j] = ~0u;
         if (p < n) {
             const uint32_t rid = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u), rank = mt[j] >> 16;
-            const uint32_t d = run_dest[lo + rid] + rank;
-            const uint32_t qq = (run_info[lo + rid] & 0xffffu) + rank;
+            const bool head = rid < (uint32_t)RUN_HEAD;
+            const uint32_t d = (head ? s_rd[rid] : run_dest[lo + rid]) + rank;
+            const uint32_t qq = (head ? s_ro[rid] : (run_info[lo + rid] & 0xffffu)) + rank;
             if (d < (uint32_t)n && qq < (uint32_t)cnt && rid == (mt[j] & 0xffffu)) {
                 dst[j] = d;
                 q[j] = qq;
@@ -2562,7 +2631,6 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
         push_f32<D, SCHEME>(t, in, P, c, o[j], u[j], kick, bad);
     }
     if (miss) flag_status(t.status, PIC_DEV_RANGE);
-    __syncthreads();   // s_dst cleared
 #pragma unroll
     for (int j = 0; j < IPT; ++j)
         if (dst[j] != ~0u) s_dst[q[j]] = dst[j];

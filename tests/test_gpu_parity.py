@@ -384,6 +384,52 @@ def test_fused_step_with_overfull_key_lists(step_rank, scheme):
             pic.tune(k, v)
 
 
+MANY_RUN_FORMS = [dict(), dict(emit_stage=0), dict(emit_stage=1), dict(emit_stage=2, emit_threads=256),
+                  dict(step_rank=1), dict(step_tile=1024, emit_threads=512)]
+
+
+@pytest.mark.parametrize("knobs", MANY_RUN_FORMS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()) or "default")
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_fused_step_with_many_runs_per_tile(scheme, knobs):
+    """A thermal spread of half the box scatters each sorted tile over a 27x27
+    tree, so tiles hold several hundred runs: more than the head of the run
+    table that the writing pass loads with the state.  The step still
+    matches the oracle."""
+    dev = _dev()
+    saved = pic.tuning()
+    try:
+        for k, v in knobs.items():
+            pic.tune(k, v)
+        tile = pic.tuning()["step_tile"]
+        rng = np.random.default_rng(47)
+        spec = W.regular_tree(2, 3)
+        n = 5 * 2048 + 333
+        x, v = rng.random((2, n)), rng.standard_normal((2, n)) * 0.5
+        o = oracle.OracleTree(spec)
+        t = _tree(spec)
+        E = W.random_field(rng, 2, o.n_vertices, 0.5)
+        st = pic.Stepper(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+        st.initial_sort()
+        xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+        st.step_fused(torch.tensor(E, device=dev), -0.9, 0.9, q_uniform=-1.0)
+        r = oracle.step(o, xs, vs, E, -0.9, 0.9, start, scheme, None, -1.0)
+        torch.cuda.synchronize()
+        # the case is the one meant: some tile has more than 256 (tile, key) runs
+        old_bin = np.repeat(np.arange(len(start) - 1), np.diff(start))
+        new_bin = np.asarray(r["new_bin"], dtype=np.int64)
+        key = 2 * new_bin + (new_bin != old_bin)
+        runs = [len(np.unique(key[a:a + tile])) for a in range(0, n, tile)]
+        assert max(runs) > 256
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+        assert np.array_equal(st.ids.cpu().numpy(), ids[r["perm"]])
+        assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        assert t.status_sync() == 0
+    finally:
+        for k, v in saved.items():
+            pic.tune(k, v)
+
+
 @pytest.mark.parametrize("spread", [0.05, 0.5])
 @pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 5 * 2048 + 3])
