@@ -424,7 +424,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
 // ------------------------------------------------------------------- rebin
 
 constexpr int RB_THREADS = 256;
-constexpr int KLIST_CAP = 64;   // runs per key listed directly by the fused step's ranking
+constexpr int KLIST_CAP = 128;  // runs per key listed directly by the fused step's ranking
 constexpr int RB_MAX_TILE = 4096;
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -979,6 +979,33 @@ __global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint3
     }
 }
 
+// Destinations of a key's 65..128 runs, two per lane: each run's
+// destination is the key base plus the counts of the runs with smaller
+// addresses, found by comparing against every run of the key in turn.
+__device__ __forceinline__ void place_counted(const RebinScratch &sc, const uint32_t *lst, uint32_t l0, uint32_t len,
+                                              uint32_t kb, int lane) {
+    uint32_t a0 = ~0u, c0 = 0u, a1 = ~0u, c1 = 0u;
+    if ((uint32_t)lane < len) {
+        a0 = lst[l0 + lane];
+        c0 = sc.run_info[a0] >> 16;
+    }
+    if ((uint32_t)lane + 64u < len) {
+        a1 = lst[l0 + 64 + lane];
+        c1 = sc.run_info[a1] >> 16;
+    }
+    uint32_t b0 = 0u, b1 = 0u;
+    for (int j = 0; j < 64; ++j) {
+        const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)a0, j);
+        const uint32_t y0 = (uint32_t)__builtin_amdgcn_readlane((int)c0, j);
+        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)a1, j);
+        const uint32_t y1 = (uint32_t)__builtin_amdgcn_readlane((int)c1, j);
+        b0 += (x0 < a0 ? y0 : 0u) + (x1 < a0 ? y1 : 0u);
+        b1 += (x0 < a1 ? y0 : 0u) + (x1 < a1 ? y1 : 0u);
+    }
+    if ((uint32_t)lane < len) sc.run_dest[a0] = kb + b0;
+    if ((uint32_t)lane + 64u < len) sc.run_dest[a1] = kb + b1;
+}
+
 __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_keys) {
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4, sub = lane & 15;
@@ -998,15 +1025,19 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
             const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
             const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
             if (glen <= 16) continue;
-            if (glen <= (uint32_t)KLIST_CAP) {
+            if (glen <= 64u) {
                 place_sorted<64>(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane);
+                continue;
+            }
+            if (glen <= (uint32_t)KLIST_CAP) {
+                place_counted(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane);
                 continue;
             }
             // a long list: gathered into its exact slot range of the list
             // array (direct part by the lanes, linked part by lane 0), then
             // every run counts the runs before it
             const uint32_t l0 = sc.list_off[gk];
-            sc.list[l0 + lane] = sc.klist[gk * KLIST_CAP + lane];
+            for (int i = lane; i < KLIST_CAP; i += 64) sc.list[l0 + i] = sc.klist[gk * KLIST_CAP + i];
             if (lane == 0) {
                 uint32_t q = KLIST_CAP;
                 for (uint32_t e = sc.khead[gk]; e != 0u && q < glen; e = sc.knext[e - 1u]) sc.list[l0 + q++] = e - 1u;

@@ -351,19 +351,21 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
             pic.tune(k, v)
 
 
+@pytest.mark.parametrize("tiles", [80, 160])
 @pytest.mark.parametrize("step_rank", [2, 1])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_fused_step_with_overfull_key_lists(step_rank, scheme):
-    """Every one of 80 tiles sends particles to every bin of a 3x3 tree, so each
-    key collects more runs than its direct list holds: the general list and
-    place passes take over, and the step still matches the oracle."""
+def test_fused_step_with_overfull_key_lists(step_rank, scheme, tiles):
+    """Every tile sends particles to every bin of a 3x3 tree, so each key
+    collects about as many runs as there are tiles: 80 take the placement by
+    counting (more than a wavefront sorts), 160 overflow the direct list into
+    the linked rest.  The step still matches the oracle."""
     dev = _dev()
     saved = pic.tuning()
     try:
         pic.tune("step_rank", step_rank)
         rng = np.random.default_rng(31)
         spec = W.regular_tree(2, 1)
-        n = 80 * 2048 + 77
+        n = tiles * 2048 + 77
         x, v = rng.random((2, n)), rng.standard_normal((2, n)) * 0.4
         o = oracle.OracleTree(spec)
         t = _tree(spec)
