@@ -23,7 +23,8 @@ SPACES = {
     "fused_f64": {"step_rank": (2, 1), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16)},
     "calls_f64": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1), "deposit_lanes": (64, 32, 16)},
-    "f32": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1), "scatter_group": (4, 2, 1)},
+    "f32": {"step_rank": (2, 0), "rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
+            "scatter_group": (4, 2, 1)},
 }
 
 

@@ -299,7 +299,8 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
     // lanes whose cell is that of the first pending lane (the id of corner 0
     // names the cell) with scalar loads, and only the lanes left gather per
     // lane.  The values, and so the arithmetic, are the same either way.
-    double Ec[1 << D][D];
+    double Ec[D == 2 ? 4 : 1][D];   // 2D: the corner values; 3D: the interpolant ef instead
+    double ef[D];
     uint64_t pend = __ballot(1);
     const uint32_t lane = __lane_id();
 #pragma unroll
@@ -312,25 +313,53 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         uint32_t vu[1 << D];
 #pragma unroll
         for (int c = 0; c < (1 << D); ++c) vu[c] = (uint32_t)__builtin_amdgcn_readlane((int)vid[c], l);
+        if constexpr (D == 2) {
 #pragma unroll
-        for (int c = 0; c < (1 << D); ++c)
+            for (int c = 0; c < (1 << D); ++c)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double eu = ld_const(P.E[j], vu[c]);
+                    if (mine) Ec[c][j] = eu;
+                }
+        } else {
+            // 3D: the 24 corner values stay in scalar registers; every lane
+            // forms this cell's interpolant (same operation order) and the
+            // lanes of the cell keep it, so no vector registers hold them
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const double eu = ld_const(P.E[j], vu[c]);
-                if (mine) Ec[c][j] = eu;
+                double e = __dmul_rn(w[0], ld_const(P.E[j], vu[0]));
+#pragma unroll
+                for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], ld_const(P.E[j], vu[c])));
+                if (mine) ef[j] = e;
             }
+        }
     }
     if ((pend >> lane) & 1ull) {
+        if constexpr (D == 2) {
 #pragma unroll
-        for (int c = 0; c < (1 << D); ++c)
+            for (int c = 0; c < (1 << D); ++c)
 #pragma unroll
-            for (int j = 0; j < D; ++j) Ec[c][j] = ld_off(P.E[j], vid[c]);
+                for (int j = 0; j < D; ++j) Ec[c][j] = ld_off(P.E[j], vid[c]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double e = __dmul_rn(w[0], ld_off(P.E[j], vid[0]));
+#pragma unroll
+                for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], ld_off(P.E[j], vid[c])));
+                ef[j] = e;
+            }
+        }
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        double e = __dmul_rn(w[0], Ec[0][j]);
+        double e;
+        if constexpr (D == 2) {
+            e = __dmul_rn(w[0], Ec[0][j]);
 #pragma unroll
-        for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ec[c][j]));
+            for (int c = 1; c < (1 << D); ++c) e = __dadd_rn(e, __dmul_rn(w[c], Ec[c][j]));
+        } else {
+            e = ef[j];
+        }
         if (EP && P.Ep[0]) P.Ep[j][p] = e;
         double vj = __dadd_rn(vv[j], __dmul_rn(qmdt, e));
         double xj = __dadd_rn(xv[j], __dmul_rn(vj, dt));
