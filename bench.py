@@ -313,7 +313,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (sharding is a design note); "
+        print("bench.py measures one GPU: the library has no multi-GPU path (how it would shard is a design note); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -1,0 +1,47 @@
+"""Host-side checks of bench.py: the per-particle byte counts behind its
+roofline figures, and the one-GPU contract.  No GPU is used."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("dim,q,calls", [(2, False, 152), (2, True, 176), (3, False, 224)])
+def test_three_call_bytes_fp64(dim, q, calls):
+    """Three calls: gather_push reads and writes x, v and writes a 4-byte bin;
+    the rebin reads the bins and reads and writes every record; the deposit
+    reads the positions (and charges)."""
+    assert bench.algorithmic_bytes(dim, q)["calls"] == calls
+
+
+@pytest.mark.parametrize("dim,calls", [(2, 80), (3, 116)])
+def test_three_call_bytes_fp32(dim, calls):
+    assert bench.algorithmic_bytes_f32(dim, False)["calls"] == calls
+
+
+def test_fused_bytes_per_pass_form():
+    """2D FP64: key pass 36, group pass 8, writing pass 68, deposit 16."""
+    ab = bench.algorithmic_bytes(2, False, 2)
+    assert (ab["step_key"], ab["step_group"], ab["step_emit"], ab["deposit_bins"]) == (36, 8, 68, 16)
+    assert ab["fused"] == 128
+    assert bench.algorithmic_bytes(2, False, 1)["fused"] == 36 + 68 + 16
+    assert bench.algorithmic_bytes(2, False, 0)["fused"] == 32 + 64 + 16
+    # every pass form moves fewer bytes than the three calls
+    for r in (0, 1, 2):
+        for dim in (2, 3):
+            for q in (False, True):
+                ab = bench.algorithmic_bytes(dim, q, r)
+                assert ab["fused"] < ab["calls"]
+
+
+def test_more_than_one_gpu_is_refused():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
+    assert res.stdout == ""
