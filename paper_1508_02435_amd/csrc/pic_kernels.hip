@@ -483,6 +483,7 @@ struct RebinScratch {
     uint32_t *klist;      // 2*n_bins * KLIST_CAP: fused step, run addresses per key (arrival order)
     uint32_t *khead;      // 2*n_bins (zeroed per call): runs of a key past KLIST_CAP, a linked list
     uint32_t *knext;      // n_tiles * TILE: next run of that list (run address + 1; 0 ends it)
+    uint32_t *wave_bin;   // n_tiles * TILE / 64: old bin of slot 64 c (sorted input), for the FP32 form
 };
 
 // Counter layout of the LDS radix passes: digit-major index f = d*256 + t,
@@ -2020,6 +2021,8 @@ __global__ void k_rebin_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_
             if (last >= s1) break;
             if (last >= s0) sc.tile_bin[2 * t + 1] = (uint32_t)(b + 1);
         }
+        // the bin of every 64th slot (a wavefront's first slot)
+        for (int64_t c = (s0 + 63) >> 6; (c << 6) < s1; ++c) sc.wave_bin[c] = (uint32_t)b;
     }
 }
 
@@ -2546,7 +2549,7 @@ __global__ __launch_bounds__(256) void k_gather_push_f32(DevTree t, DevInst in0,
 // it and in the next two bins are served from scalar loads of their bounds;
 // lanes left search on their own.
 __device__ __forceinline__ uint32_t old_bin_wave(const int64_t *start, uint32_t n_bins, const uint32_t *tile_bin,
-                                                 int tile, int64_t p) {
+                                                 int tile, int64_t p, const uint32_t *wave_bin) {
     uint64_t pend = __ballot(1);
     const uint32_t lane = __lane_id();
     const int l = __builtin_ctzll(pend);
@@ -2554,7 +2557,10 @@ __device__ __forceinline__ uint32_t old_bin_wave(const int64_t *start, uint32_t 
                                  ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)p >> 32), l)
                                   << 32));
     uint32_t lo = 0, hi = n_bins - 1u;
-    if (tile_bin) {
+    if (wave_bin) {
+        // the bin of the first slot of pu's group of 64: one load, no search
+        lo = hi = min(ld_const(wave_bin, (uint32_t)(pu >> 6)), n_bins - 1u);
+    } else if (tile_bin) {
         const int64_t tl = pu / tile;
         lo = min(ld_const(tile_bin, (uint32_t)(2 * tl)), n_bins - 1u);
         hi = min(max(ld_const(tile_bin, (uint32_t)(2 * tl + 1)), lo + 1u), n_bins) - 1u;
@@ -2587,7 +2593,7 @@ __global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F3
                                                       double dt0, const double *qa, const double *da,
                                                       const int64_t *inst_start, const int64_t *bin_start,
                                                       uint32_t n_bins, const uint32_t *tile_bin, int tile,
-                                                      uint32_t *key_out) {
+                                                      uint32_t *key_out, const uint32_t *wave_bin) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         int ii = 0;
@@ -2603,7 +2609,7 @@ __global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F3
             o[k] = P.off[k][p];
             u[k] = P.u[k][p];
         }
-        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, tile, p);
+        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, tile, p, wave_bin);
         uint32_t c[D];
         cell_of<D, SCHEME>(t, in, local_rank<SCHEME>(in, ob, bad), o, c);
         uint32_t nb = push_f32<D, SCHEME>(t, in, P, c, o, u, kick, bad);
@@ -2623,7 +2629,8 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
                                                       const int64_t *inst_start, const int64_t *bin_start,
                                                       uint32_t n_bins, const uint32_t *tile_bin,
                                                       const uint32_t *meta, const uint32_t *run_dest,
-                                                      const uint32_t *run_info, F32Ptrs out, Cols extra, int xcd) {
+                                                      const uint32_t *run_info, F32Ptrs out, Cols extra, int xcd,
+                                                      const uint32_t *wave_bin) {
     constexpr int IPT = TILE / NT;
     __shared__ uint64_t s_val[TILE];
     __shared__ uint32_t s_dst[TILE];
@@ -2685,7 +2692,7 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
         const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
         const double dt = (MULTI && da) ? da[ii] : dt0;
         const float kick = (float)(qmdt * dt * in.Sd);
-        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, TILE, p);
+        const uint32_t ob = old_bin_wave(bin_start, n_bins, tile_bin, TILE, p, wave_bin);
         uint32_t c[D];
         cell_of<D, SCHEME>(t, in, local_rank<SCHEME>(in, ob, bad), o[j], c);
         push_f32<D, SCHEME>(t, in, P, c, o[j], u[j], kick, bad);
@@ -2964,7 +2971,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_cn, key_base,
         list_off,
-        list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, total;
+        list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, wave_bin, total;
 };
 
 static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
@@ -2995,6 +3002,7 @@ static RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.keys = o; o = align256(o + slots * 4);
     L.klist = o; o = align256(o + keys * KLIST_CAP * 4);
     L.knext = o; o = align256(o + slots * 4);
+    L.wave_bin = o; o = align256(o + (slots / 64 + 1) * 4);
     L.total = o;
     return L;
 }
@@ -3060,6 +3068,7 @@ static RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.klist = (uint32_t *)(base + L.klist);
     sc.khead = (uint32_t *)(base + L.khead);
     sc.knext = (uint32_t *)(base + L.knext);
+    sc.wave_bin = (uint32_t *)(base + L.wave_bin);
     return sc;
 }
 
@@ -3388,14 +3397,14 @@ static void step_passes_f32(const pic_tree *t, const F32Ptrs &P, const F32Ptrs &
     const int64_t tiles = (n + TILE - 1) / TILE;
     PIC_LAUNCH("step_key_f32", (k_step_key_f32<D, SCH, MULTI>), dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
                t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
-               TILE, sc.keys);
+               TILE, sc.keys, (const uint32_t *)sc.wave_bin);
     PIC_LAUNCH("step_group", (k_step_group<8>), dim3(tiles), dim3(RB_THREADS), 0, s, (const uint32_t *)sc.keys, n, sc,
                sc.meta, 0);
     launch_step_middle(t, n, n_bins, sc, new_start, s);
     PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024>), dim3(tiles), dim3(1024), 0, s, t->dt,
                t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
                (const uint32_t *)sc.meta, (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, Q, extra,
-               g_tune.xcd_tiles);
+               g_tune.xcd_tiles, (const uint32_t *)sc.wave_bin);
 }
 
 hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
