@@ -60,10 +60,10 @@ def algorithmic_bytes_f32(dim: int, per_particle_q: bool):
     }
 
 
-def algorithmic_bytes(dim: int, per_particle_q: bool, step_rank: int = 2):
+def algorithmic_bytes(dim: int, per_particle_q: bool):
     """Bytes each kernel must move per particle (FP64 form).  "calls" is the
-    three-call path (gather_push, rebin, deposit); "fused" is pic_step in the
-    pass form selected by the step_rank knob."""
+    three-call path (gather_push, rebin, deposit); "fused" is pic_step (key,
+    group and emit passes, then the deposit)."""
     s_push = 2 * 8 * dim                   # x, v
     q = 8 if per_particle_q else 0
     s_rec = s_push + q                     # a full record moved by a rebin
@@ -73,17 +73,12 @@ def algorithmic_bytes(dim: int, per_particle_q: bool, step_rank: int = 2):
         "rebin_tiles": 4,                  # new bins read
         "rebin_scatter": 2 * s_rec,        # every record read and written once
         "deposit_bins": s_dep,
-        "step_count": s_push,              # x, v read
-        "step_move": s_push + s_rec + q,   # x, v (and q) read, the full record written
         "step_key": s_push + 4,            # x, v read, key written
         "step_group": 4 + 4,               # key read, run index | rank written
-        "step_rank": s_push + 4,           # x, v read, run index | rank written
         "step_emit": s_push + 4 + s_rec + q,   # x, v, run index | rank (and q) read, the record written
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
     }
-    ab["fused"] = {0: ab["step_count"] + ab["step_move"],
-                   1: ab["step_rank"] + ab["step_emit"],
-                   2: ab["step_key"] + ab["step_group"] + ab["step_emit"]}[step_rank] + s_dep
+    ab["fused"] = ab["step_key"] + ab["step_group"] + ab["step_emit"] + s_dep
     return ab
 
 
@@ -243,7 +238,7 @@ def run_batched(args, scheme):
     kt = kernel_times(lib)
     lib.pic_profile_enable(0)
     per_kernel = {k: {"launches": a, "avg_ms": tot / a} for k, (a, tot) in kt.items()}
-    ab = algorithmic_bytes(2, False, pic.tuning()["step_rank"])
+    ab = algorithmic_bytes(2, False)
     dominant = max((k for k in per_kernel if k in ab), key=lambda k: per_kernel[k]["avg_ms"])
     achieved = ab[dominant] * n / (per_kernel[dominant]["avg_ms"] * 1e-3) / 1e9
     del st
@@ -350,7 +345,7 @@ def main():
     _log(f"[bench] n={wl.n} leaves={tree.n_leaves} path={args.path} warmup={args.warmup} steps={args.steps}")
     lib = pic.lib()
     ab = (algorithmic_bytes_f32(wl.dim, wl.q is not None) if f32 else
-          algorithmic_bytes(wl.dim, wl.q is not None, pic.tuning()["step_rank"]))
+          algorithmic_bytes(wl.dim, wl.q is not None))
     # Warmup; its last step is profiled (every launch bracketed by events) to
     # name the dominant kernel.  The field is prescribed, not solved, so the
     # particles drift away from the stated distribution as steps go on (they

@@ -139,7 +139,8 @@ pic_status pic_tree_pidt_table(const pic_tree *tree, uint64_t *pidt_key, int32_t
 /*
  * Copy the device tables into `buffer_dev` (at least info.device_bytes
  * bytes, 256-byte aligned) and bind them to `tree`.  The buffer also holds
- * the sticky status word, cleared here.  Enqueued on `stream`; the host
+ * the sticky status word, cleared here.  The copy runs on `stream` and the
+ * call waits for it (synchronises `stream`) before returning; the host
  * tables stay owned by `tree`.
  */
 pic_status pic_tree_upload(pic_tree *tree, void *buffer_dev, size_t bytes, void *stream);
@@ -228,6 +229,36 @@ pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precisi
 size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_t precision);
 
 /*
+ * Re-bin statistics (paper Sec. 6.1: lifts per particle and time step).  In
+ * the paper's PIT a particle that leaves its leaf is lifted towards the root
+ * until a cell covers it and dropped from there into its new leaf, so a
+ * particle moving from leaf a to leaf b is lifted level(a) - level(c) times,
+ * c the coarsest common ancestor of a and b ("n levels = n lifts").  For PIDT
+ * the same count is taken in the dual tree (dual cells of a k = 3 tree nest,
+ * Sec. 4.1): c is the coarsest dual cell holding the old and the new one.
+ * Device record of 64-bit counters, nullable wherever it is accepted.  The
+ * calls ADD to it (integer atomics, so the result is deterministic); zero it
+ * once and it accumulates over steps.  Layout:
+ *   particles   particles counted (n per call);
+ *   movers      particles whose new bin differs from their old one;
+ *   lifts       sum of the lift counts (0 for particles that stay);
+ *   max_tunnel  largest periodic max-norm distance, in finest cells of the
+ *               instance, between a particle's old and new bin anchor (leaf
+ *               lower corner for PIT, vertex position for PIDT); this is the
+ *               maximum only, the other fields are sums;
+ *   lift_hist   particles by lift count (entry 0: particles that stayed; the
+ *               last entry also counts larger counts).
+ */
+#define PIC_STATS_LEVELS 20
+typedef struct {
+    uint64_t particles;
+    uint64_t movers;
+    uint64_t lifts;
+    uint64_t max_tunnel;
+    uint64_t lift_hist[PIC_STATS_LEVELS];
+} pic_rebin_stats;
+
+/*
  * Re-bin (paper Sec. 5: after the move every particle is held by the grid
  * entity covering it; Theorems 1 and 2; "bucket sort" into children).
  * Output order: bins ascending; inside a bin first the particles that were
@@ -240,12 +271,14 @@ size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_
  *                      (element size 4 or 8 bytes); outputs must not alias
  *                      inputs.
  *   new_bin_start_dev  receives n_bins+1 int64 offsets of the output.
+ *   stats_dev          nullable pic_rebin_stats record the call adds to (needs
+ *                      old_bin_start_dev; PIC_E_ARG without it).
  */
 pic_status pic_rebin(const pic_tree *tree, int32_t scheme, int64_t n,
                      const uint32_t *new_bin_dev, const int64_t *old_bin_start_dev,
                      int32_t n_cols, void *const *cols_in_dev, void *const *cols_out_dev,
                      const int32_t *col_bytes, int64_t *new_bin_start_dev,
-                     void *scratch_dev, size_t scratch_bytes, void *stream);
+                     void *scratch_dev, size_t scratch_bytes, pic_rebin_stats *stats_dev, void *stream);
 
 /*
  * Deposit (paper Sec. 3 step 1): rho_v = sum_p q_p w_v(x_p) for a sorted set
@@ -263,10 +296,8 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
 /*
  * One whole step in a single call: the same result as pic_gather_push, then
  * pic_rebin (in -> out) and pic_deposit (on out) (paper Sec. 3 steps 1, 3, 4;
- * Sec. 5 re-binning).  `in` stays unchanged (both forms, unless the knob
- * "step_rank" is 0, where the FP32 form pushes `in` in place first): a key
- * pass pushes every particle and writes its key 2 * new bin + arrived; a
- * group pass ranks every particle among the particles of its tile with the
+ * Sec. 5 re-binning).  `in` stays unchanged: a key pass pushes every
+ * particle and writes its key 2 * new bin + arrived; a group pass ranks every particle among the particles of its tile with the
  * same key, in tile order; a scan and a placement give every run (tile, key)
  * its destination; an emit pass pushes each particle again (the same
  * arithmetic, so the same state and bin) and writes it to its run's
@@ -278,6 +309,7 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
  *                      columns (8-byte), or -1 to use q_uniform.
  *   out                receives the re-binned set; new_bin_start_dev its
  *                      offsets; rho_dev the vertex charge.
+ *   stats_dev          nullable pic_rebin_stats record the call adds to.
  * Scratch: pic_scratch_bytes().  E_p is not produced.
  */
 pic_status pic_step(const pic_tree *tree, int32_t scheme, int32_t precision, pic_particles *in,
@@ -285,7 +317,7 @@ pic_status pic_step(const pic_tree *tree, int32_t scheme, int32_t precision, pic
                     const pic_push_params *params, int32_t n_extra, void *const *extra_in_dev,
                     void *const *extra_out_dev, const int32_t *extra_bytes, int32_t q_column, double q_uniform,
                     pic_particles *out, int64_t *new_bin_start_dev, double *rho_dev, void *scratch_dev,
-                    size_t scratch_bytes, void *stream);
+                    size_t scratch_bytes, pic_rebin_stats *stats_dev, void *stream);
 
 /*
  * Convert a particle set between the FP64 form and the FP32 offset form
@@ -340,7 +372,11 @@ pic_status pic_profile_enable(int32_t on);
 pic_status pic_profile_only(const char *name);
 
 /*
- * Launch-shape knobs, for the autotuner.  Names and values:
+ * Launch-shape knobs, for the autotuner.  Every tree carries its own set:
+ * pic_tree_tune_set / pic_tree_tune_get change and read the knobs of one
+ * tree (and so every call made with it afterwards); pic_tune_set /
+ * pic_tune_get change and read the process defaults, which a tree copies
+ * when it is created.  Names and values:
  *   "rebin_tile"    particles per rebin tile, 2048 or 4096 (default 2048);
  *   "rebin_radix"   bits per LDS radix pass of the tile sort, 4 or 5 (default 4);
  *   "scatter_mode"  0 = records staged through LDS, 1 = gathered straight from
@@ -349,22 +385,15 @@ pic_status pic_profile_only(const char *name);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
  *   "deposit_bpw"   bins such a lane group takes one after the other, 1 or 2 (default 1);
- *   "step_tile"     particles per tile of pic_step's two passes, 1024 or 2048 (default 2048);
- *   "step_rank"     pic_step's passes: 1 = the first pass ranks every particle inside
- *                   its tile and the second only pushes and writes, 2 = as 1 with the
- *                   first pass split into a push pass that writes keys and a tile
- *                   ranking pass over those keys, 0 = the first pass only counts and
- *                   the second ranks (default 2);
+ *   "step_tile"     particles per tile of pic_step's ranking and writing passes,
+ *                   1024 or 2048 (default 2048);
  *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's
  *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
- *   "emit_stage"    the writing pass of pic_step stages 1 or 2 columns at a time
- *                   through LDS in tile-sorted order, or 0 = stores straight from
- *                   registers (default 2);
- *   "emit_threads"  threads per block of that pass, 256, 512 or 1024 (default 1024);
- *   "regular_tables" 1 = trees created afterwards get Peano rank tables for their
- *                   regular instances (up to 2^21 cells per level), which the
- *                   arithmetic kernels and the FP32 form use; 0 = none, every
- *                   tree takes the descent kernels (default 1).
+ *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);
+ *   "regular_tables" (process default only) 1 = trees created afterwards get Peano
+ *                   rank tables for their regular instances (up to 2^21 cells per
+ *                   level), which the arithmetic kernels and the FP32 form use;
+ *                   0 = none, every tree takes the descent kernels (default 1).
  * Every setting gives the same bins, order and particle state; "deposit_lanes"
  * changes the order of the deposit's sums, so the charge differs in rounding
  * only (far inside the stated tolerance).  pic_scratch_bytes covers all settings.
@@ -373,6 +402,8 @@ pic_status pic_profile_only(const char *name);
  */
 pic_status pic_tune_set(const char *name, int64_t value);
 int64_t pic_tune_get(const char *name);
+pic_status pic_tree_tune_set(pic_tree *tree, const char *name, int64_t value);
+int64_t pic_tree_tune_get(const pic_tree *tree, const char *name);
 int32_t pic_profile_read(pic_kernel_time *out, int32_t max_entries);
 
 #ifdef __cplusplus

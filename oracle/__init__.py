@@ -14,6 +14,7 @@ Paper sections followed (see the C file header for the readings):
   Sec. 5.1 PIT: each particle held by the leaf covering it (Theorem 1).
   Sec. 5.2 PIDT: each particle held by the vertex whose dual cell covers it
            (Theorem 2).
+  Sec. 6.1 lifts per particle and step (re-bin statistics).
   App. A   Langmuir-wave units and the Bohm-Gross relation.
 """
 from __future__ import annotations
@@ -29,6 +30,7 @@ _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB = os.path.join(_HERE, "_pic_oracle.so")
 
 PIT, PIDT = 0, 1
+STATS_LEVELS = 20   # entries of the lift-count histogram
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +83,8 @@ def _declare(L):
     L.orc_rebin.argtypes = [i64, i64, vp, vp, vp, vp]
     L.orc_deposit.restype = i32
     L.orc_deposit.argtypes = [vp, i64, vp, vp, dbl, vp]
+    L.orc_rebin_stats.restype = i32
+    L.orc_rebin_stats.argtypes = [vp, i32, i64, vp, vp, i32, vp]
 
 
 def _p(a):
@@ -198,6 +202,18 @@ class OracleTree:
     def bin_of(self, x, scheme):
         leaf, pidt, _ = self.locate(x)
         return leaf if scheme == PIT else pidt
+
+    def rebin_stats(self, old_start, new_bin, scheme, n_hist: int = STATS_LEVELS):
+        """Re-bin statistics of a sorted set (offsets ``old_start``) moving to
+        ``new_bin`` (paper Sec. 6.1, lifts per particle): dict of particles,
+        movers, lifts, max_tunnel and lift_hist."""
+        os_ = np.ascontiguousarray(old_start, np.int64)
+        nb = np.ascontiguousarray(new_bin, np.int32)
+        out = np.zeros(4 + n_hist, np.int64)
+        if self._L.orc_rebin_stats(self._h, int(scheme), nb.size, _p(os_), _p(nb), n_hist, _p(out)):
+            raise ValueError("oracle: bad offsets or bins")
+        return {"particles": int(out[0]), "movers": int(out[1]), "lifts": int(out[2]), "max_tunnel": int(out[3]),
+                "lift_hist": [int(v) for v in out[4:]]}
 
 
 def rebin(new_bin, n_bins: int, old_start=None):

@@ -541,3 +541,79 @@ int orc_deposit(void *h, int64_t n, const double *x, const double *q, double q_u
     free(comp);
     return 0;
 }
+
+/* ---------------------------------------------------------------- re-bin statistics */
+/* Lifts per particle (paper Sec. 6.1; PIT, Sec. 5.1): a particle that leaves
+   its leaf a is lifted to the parent cell until a cell covers it, then
+   dropped into its new leaf b, so it is lifted level(a) - level(c) times, c
+   the coarsest common ancestor of a and b.  The ancestor of a level-l cell
+   with coordinates a at level m <= l has coordinates a / 3^(l-m); c is the
+   finest level m <= min(level(a), level(b)) at which the two ancestors
+   agree.  PIDT: the same in the dual tree.  Dual cells of a k = 3 tree nest
+   (Sec. 4.1): the dual cell of the level-l vertex b covers, per axis, the
+   finest vertices within (3^(L-l) - 1)/2 of b 3^(L-l), which on the lattice
+   shifted by (3^L - 1)/2 is the aligned level-l block number
+   (b + (3^l - 1)/2) mod 3^l; its ancestors are taken on those numbers.
+   Tunnel distance: the periodic max-norm distance between the old and new
+   bin's anchor (leaf lower corner, or vertex position) in finest units.
+   out: particles, movers, lifts, max_tunnel, hist[n_hist] (particles by lift
+   count, the last entry also counting larger ones); added to. */
+static void bin_cell(const otree *t, int scheme, int64_t b, int *level, int64_t *a, int64_t *anchor)
+{
+    if (scheme == 0) {
+        const onode *nd = &t->nodes[t->leaf_node[b]];
+        *level = nd->level;
+        for (int k = 0; k < t->dim; ++k) {
+            a[k] = nd->a[k];
+            anchor[k] = nd->a[k] * ipow3(t->L - nd->level);
+        }
+    } else {
+        const int l = t->pidt_level[b];
+        const int64_t nl = ipow3(l);
+        *level = l;
+        for (int k = 0; k < t->dim; ++k) {
+            const int64_t bk = t->pidt_b[b * t->dim + k];
+            a[k] = (bk + (nl - 1) / 2) % nl;
+            anchor[k] = bk * ipow3(t->L - l);
+        }
+    }
+}
+
+int orc_rebin_stats(void *h, int scheme, int64_t n, const int64_t *old_start, const int32_t *new_bin,
+                    int n_hist, int64_t *out)
+{
+    otree *t = (otree *)h;
+    const int64_t n_bins = scheme == 0 ? t->n_leaves : t->n_pidt;
+    if (old_start[0] != 0 || old_start[n_bins] != n) return -1;
+    out[0] += n;
+    for (int64_t b0 = 0; b0 < n_bins; ++b0) {
+        for (int64_t p = old_start[b0]; p < old_start[b0 + 1]; ++p) {
+            const int64_t b1 = new_bin[p];
+            if (b1 < 0 || b1 >= n_bins) return -1;
+            if (b1 == b0) { out[4] += 1; continue; }
+            int l0, l1;
+            int64_t a0[MAXD], a1[MAXD], A0[MAXD], A1[MAXD];
+            bin_cell(t, scheme, b0, &l0, a0, A0);
+            bin_cell(t, scheme, b1, &l1, a1, A1);
+            int m = l0 < l1 ? l0 : l1;
+            for (; m > 0; --m) {
+                int same = 1;
+                for (int k = 0; k < t->dim; ++k)
+                    if (a0[k] / ipow3(l0 - m) != a1[k] / ipow3(l1 - m)) same = 0;
+                if (same) break;
+            }
+            int64_t dist = 0;
+            for (int k = 0; k < t->dim; ++k) {
+                int64_t d = A0[k] > A1[k] ? A0[k] - A1[k] : A1[k] - A0[k];
+                if (t->S - d < d) d = t->S - d;
+                if (d > dist) dist = d;
+            }
+            const int lifts = l0 - m;
+            out[1] += 1;
+            out[2] += lifts;
+            if (dist > out[3]) out[3] = dist;
+            out[4 + (lifts < n_hist ? lifts : n_hist - 1)] += 1;
+        }
+    }
+    return 0;
+}

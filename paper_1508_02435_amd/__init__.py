@@ -19,7 +19,8 @@ from . import _capi
 from ._capi import F32_OFFSET, F64, PIDT, PIT, PicError, check, lib
 
 __all__ = ["Tree", "PIT", "PIDT", "F64", "F32_OFFSET", "PicError", "locate", "gather_push", "rebin",
-           "deposit", "scratch_bytes", "Stepper", "Stepper32", "lib", "tune", "tuning", "TUNING_KNOBS", "step"]
+           "deposit", "scratch_bytes", "Stepper", "Stepper32", "lib", "tune", "tuning", "TUNING_KNOBS", "step",
+           "new_stats", "read_stats"]
 
 
 def _ptr(t) -> Optional[int]:
@@ -169,18 +170,39 @@ def _check_inst(tree, inst_start):
 
 
 TUNING_KNOBS = {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1), "scatter_nt": (0, 1),
-                "scatter_group": (1, 2, 4), "deposit_lanes": (16, 32, 64), "step_tile": (2048, 1024), "regular_tables": (1, 0),
-                "step_rank": (2, 1, 0), "xcd_tiles": (1, 0), "emit_stage": (2, 1, 0),
-                "emit_threads": (1024, 512, 256), "deposit_bpw": (1, 2)}
+                "scatter_group": (1, 2, 4), "deposit_lanes": (16, 32, 64), "step_tile": (2048, 1024),
+                "xcd_tiles": (1, 0), "emit_threads": (1024, 512), "deposit_bpw": (1, 2), "regular_tables": (1, 0)}
+PROCESS_ONLY = ("regular_tables",)   # read when a tree is created; not a knob of a tree
 
 
-def tune(name: str, value: int):
-    """Set a launch-shape knob (results do not depend on it)."""
-    check(lib().pic_tune_set(name.encode(), int(value)), f"pic_tune_set({name}={value})")
+def tune(name: str, value: int, tree: Optional["Tree"] = None):
+    """Set a launch-shape knob (results do not depend on it): of one tree, or
+    the process default that trees created afterwards copy."""
+    if tree is None:
+        check(lib().pic_tune_set(name.encode(), int(value)), f"pic_tune_set({name}={value})")
+    else:
+        check(lib().pic_tree_tune_set(tree.handle, name.encode(), int(value)), f"pic_tree_tune_set({name}={value})")
 
 
-def tuning() -> dict:
-    return {k: int(lib().pic_tune_get(k.encode())) for k in TUNING_KNOBS}
+def tuning(tree: Optional["Tree"] = None) -> dict:
+    """Knob values of one tree, or the process defaults."""
+    if tree is None:
+        return {k: int(lib().pic_tune_get(k.encode())) for k in TUNING_KNOBS}
+    return {k: int(lib().pic_tree_tune_get(tree.handle, k.encode())) for k in TUNING_KNOBS if k not in PROCESS_ONLY}
+
+
+def new_stats(device="cuda"):
+    """A zeroed device record for the re-bin statistics (int64 words)."""
+    import torch
+    return torch.zeros(_capi.STATS_WORDS, dtype=torch.int64, device=device)
+
+
+def read_stats(stats) -> dict:
+    """The re-bin statistics record as a dict (particles, movers, lifts,
+    max_tunnel, lift_hist)."""
+    a = stats.cpu().numpy()
+    return {"particles": int(a[0]), "movers": int(a[1]), "lifts": int(a[2]), "max_tunnel": int(a[3]),
+            "lift_hist": [int(x) for x in a[4:4 + _capi.STATS_LEVELS]]}
 
 
 def scratch_bytes(tree: Tree, n: int, scheme: int, precision: int = F64) -> int:
@@ -222,7 +244,7 @@ def gather_push(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_ou
 
 
 def rebin(tree: Tree, scheme: int, new_bin, old_start, cols_in: Sequence, cols_out: Sequence, new_start,
-          scratch, stream=None):
+          scratch, stats=None, stream=None):
     """Stable re-bin; permutes every column of cols_in into cols_out."""
     n = new_bin.numel()
     _check_vec(new_bin, n, "new_bin")
@@ -242,7 +264,16 @@ def rebin(tree: Tree, scheme: int, new_bin, old_start, cols_in: Sequence, cols_o
     check(lib().pic_rebin(tree.handle, scheme, n, C.c_void_p(_ptr(new_bin)),
                           C.c_void_p(_ptr(old_start)) if old_start is not None else None,
                           nc, ins, outs, sizes, C.c_void_p(_ptr(new_start)), C.c_void_p(_ptr(scratch)),
-                          scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))), "pic_rebin")
+                          scratch.numel() * scratch.element_size(), _stats_ptr(stats),
+                          C.c_void_p(_stream(stream))), "pic_rebin")
+
+
+def _stats_ptr(stats):
+    if stats is None:
+        return None
+    _check_vec(stats, _capi.STATS_WORDS, "stats")
+    _need(stats.element_size() == 8, "stats: 64-bit words expected")
+    return C.c_void_p(_ptr(stats))
 
 
 def deposit(tree: Tree, scheme: int, x, bin_start, rho, scratch, q=None, q_uniform: float = 0.0,
@@ -265,7 +296,7 @@ def deposit(tree: Tree, scheme: int, x, bin_start, rho, scratch, q=None, q_unifo
 
 def step(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_start, x_out, v_out, new_start, rho,
          scratch, extra_in=(), extra_out=(), q_column: int = -1, q_uniform: float = 0.0, inst_start=None,
-         qmdt_dev=None, dt_dev=None, stream=None):
+         qmdt_dev=None, dt_dev=None, stats=None, stream=None):
     """Fused whole step (gather+push, re-bin into x_out/v_out, deposit); x, v are consumed."""
     n = x.shape[1]
     for a, nm in ((x, "x"), (v, "v"), (x_out, "x_out"), (v_out, "v_out")):
@@ -295,7 +326,8 @@ def step(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_start, x_
     check(lib().pic_step(tree.handle, scheme, F64, C.byref(P), C.c_void_p(_ptr(bin_start)), Eptr, float(qmdt),
                          float(dt), C.byref(pp), ne, ins, outs, sizes, int(q_column), float(q_uniform), C.byref(Q),
                          C.c_void_p(_ptr(new_start)), C.c_void_p(_ptr(rho)), C.c_void_p(_ptr(scratch)),
-                         scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))), "pic_step")
+                         scratch.numel() * scratch.element_size(), _stats_ptr(stats), C.c_void_p(_stream(stream))),
+          "pic_step")
 
 
 class Stepper:
@@ -357,22 +389,22 @@ class Stepper:
         gather_push(self.tree, self.scheme, self.x, self.v, E, qmdt, dt, self.bin,
                     Ep=self.Ep if want_Ep else None, inst_start=self.inst_start, **kw)
 
-    def rebin(self):
+    def rebin(self, stats=None):
         ins, outs = self._cols((self.x, self.v, self.q, self.ids), (self.x2, self.v2, self.q2, self.ids2))
-        rebin(self.tree, self.scheme, self.bin, self.start, ins, outs, self.start2, self.scratch)
+        rebin(self.tree, self.scheme, self.bin, self.start, ins, outs, self.start2, self.scratch, stats=stats)
         self._swap()
 
     def deposit(self, q_uniform=0.0):
         deposit(self.tree, self.scheme, self.x, self.start, self.rho, self.scratch, q=self.q,
                 q_uniform=q_uniform, inst_start=self.inst_start)
 
-    def step(self, E, qmdt, dt, q_uniform=0.0, **kw):
+    def step(self, E, qmdt, dt, q_uniform=0.0, stats=None, **kw):
         """Three separate calls: gather_push, rebin, deposit."""
         self.gather_push(E, qmdt, dt, **kw)
-        self.rebin()
+        self.rebin(stats)
         self.deposit(q_uniform)
 
-    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None, stats=None):
         """The same step through the single fused call."""
         extra_in, extra_out = [], []
         q_col = -1
@@ -383,7 +415,7 @@ class Stepper:
             extra_in.append(self.ids); extra_out.append(self.ids2)
         step(self.tree, self.scheme, self.x, self.v, E, qmdt, dt, self.start, self.x2, self.v2, self.start2,
              self.rho, self.scratch, extra_in, extra_out, q_col, q_uniform, inst_start=self.inst_start,
-             qmdt_dev=qmdt_dev, dt_dev=dt_dev)
+             qmdt_dev=qmdt_dev, dt_dev=dt_dev, stats=stats)
         self._swap()
 
 
@@ -454,9 +486,9 @@ class Stepper32:
         self.ids, self.ids2 = self.ids2, self.ids
         self.start, self.start2 = self.start2, self.start
 
-    def _rebin(self, old_start):
+    def _rebin(self, old_start, stats=None):
         ins, outs = self._cols()
-        rebin(self.tree, self.scheme, self.bin, old_start, ins, outs, self.start2, self.scratch)
+        rebin(self.tree, self.scheme, self.bin, old_start, ins, outs, self.start2, self.scratch, stats=stats)
         self._swap()
 
     def to_f64(self):
@@ -467,7 +499,7 @@ class Stepper32:
         self._convert(F64, xd, vd, self.start)
         return xd, vd
 
-    def step(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+    def step(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None, stats=None):
         """Three separate calls: gather_push (in place), rebin, deposit."""
         for k in range(self.tree.dim):
             _check_vec(E[k], self.tree.n_vertices, f"E[{k}]")
@@ -478,7 +510,7 @@ class Stepper32:
                                     float(dt), C.byref(pp), C.c_void_p(_ptr(self.start)),
                                     C.c_void_p(_ptr(self.bin)), None, C.c_void_p(_stream(None))),
               "pic_gather_push")
-        self._rebin(self.start)
+        self._rebin(self.start, stats)
         self.deposit(q_uniform)
 
     def deposit(self, q_uniform=0.0):
@@ -490,7 +522,7 @@ class Stepper32:
                                 self.scratch.numel() * self.scratch.element_size(), C.c_void_p(_stream(None))),
               "pic_deposit")
 
-    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None):
+    def step_fused(self, E, qmdt, dt, q_uniform=0.0, qmdt_dev=None, dt_dev=None, stats=None):
         """The same step through the single call pic_step (FP32 form)."""
         for k in range(self.tree.dim):
             _check_vec(E[k], self.tree.n_vertices, f"E[{k}]")
@@ -512,7 +544,8 @@ class Stepper32:
                              Eptr, float(qmdt), float(dt), C.byref(pp), ne, ins, outs, sizes, q_col,
                              float(q_uniform), C.byref(Q), C.c_void_p(_ptr(self.start2)),
                              C.c_void_p(_ptr(self.rho)), C.c_void_p(_ptr(self.scratch)),
-                             self.scratch.numel() * self.scratch.element_size(), C.c_void_p(_stream(None))),
+                             self.scratch.numel() * self.scratch.element_size(), _stats_ptr(stats),
+                             C.c_void_p(_stream(None))),
               "pic_step")
         self._swap()
 

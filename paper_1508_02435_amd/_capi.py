@@ -18,7 +18,11 @@ EXPORTS = [
     "pic_status_sync", "pic_status_string", "pic_locate", "pic_gather_push", "pic_scratch_bytes",
     "pic_rebin", "pic_deposit", "pic_stream_push", "pic_profile_enable", "pic_profile_read",
     "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only", "pic_convert",
+    "pic_tree_tune_set", "pic_tree_tune_get",
 ]
+
+STATS_LEVELS = 20          # PIC_STATS_LEVELS
+STATS_WORDS = 4 + STATS_LEVELS   # pic_rebin_stats: particles, movers, lifts, max_tunnel, lift_hist[]
 
 
 class TreeInfo(C.Structure):
@@ -91,7 +95,7 @@ def lib():
         L.pic_gather_push.restype = i32
         L.pic_scratch_bytes.argtypes = [vp, i64, i32, i32]
         L.pic_scratch_bytes.restype = sz
-        L.pic_rebin.argtypes = [vp, i32, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.pic_rebin.argtypes = [vp, i32, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, vp]
         L.pic_rebin.restype = i32
         L.pic_deposit.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, vp, vp, sz, vp]
         L.pic_deposit.restype = i32
@@ -104,7 +108,7 @@ def lib():
         L.pic_profile_read.argtypes = [vp, i32]
         L.pic_profile_read.restype = i32
         L.pic_step.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, dbl, C.POINTER(PushParams), i32,
-                               vp, vp, vp, i32, dbl, C.POINTER(Particles), vp, vp, vp, sz, vp]
+                               vp, vp, vp, i32, dbl, C.POINTER(Particles), vp, vp, vp, sz, vp, vp]
         L.pic_step.restype = i32
         L.pic_convert.argtypes = [vp, i32, i32, C.POINTER(Particles), dbl, C.POINTER(PushParams), vp, vp, vp]
         L.pic_convert.restype = i32
@@ -112,6 +116,10 @@ def lib():
         L.pic_tune_set.restype = i32
         L.pic_tune_get.argtypes = [C.c_char_p]
         L.pic_tune_get.restype = i64
+        L.pic_tree_tune_set.argtypes = [vp, C.c_char_p, i64]
+        L.pic_tree_tune_set.restype = i32
+        L.pic_tree_tune_get.argtypes = [vp, C.c_char_p]
+        L.pic_tree_tune_get.restype = i64
         _lib = L
     return _lib
 

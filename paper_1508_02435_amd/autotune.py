@@ -1,8 +1,8 @@
 """Launch-shape autotuner for a stepper's time step.
 
 The launch-shape knobs of libpic (tile sizes of the re-bin and of the fused
-step, radix width, scatter staging and grouping, lanes per deposit bin) never
-change results; they only change speed, and the best values depend on the
+step, radix width, scatter staging and grouping, threads of the writing pass,
+lanes per deposit bin) never change results; they only change speed, and the best values depend on the
 workload (dimension, particles per bin, how far particles move, how many
 instances a forest holds).  ``autotune`` times every setting of the knobs that
 matter for the chosen path on the actual state, restores the state after each
@@ -16,21 +16,22 @@ import json
 import os
 from typing import Dict, Optional
 
-from . import F32_OFFSET, Stepper32, tune, tuning
+from . import Stepper32, tune, tuning
 
 # knobs each path depends on
 SPACES = {
-    "fused_f64": {"step_rank": (2, 1), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16)},
+    "fused_f64": {"step_tile": (2048, 1024), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16)},
     "calls_f64": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1), "deposit_lanes": (64, 32, 16)},
-    "f32": {"step_rank": (2, 0), "rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
-            "scatter_group": (4, 2, 1)},
+    "f32": {"xcd_tiles": (1, 0)},
+    "calls_f32": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
+                  "scatter_group": (4, 2, 1)},
 }
 
 
 def _path(stepper, fused: bool) -> str:
     if isinstance(stepper, Stepper32):
-        return "f32"
+        return "f32" if fused else "calls_f32"
     return "fused_f64" if fused else "calls_f64"
 
 
@@ -66,30 +67,32 @@ def _time_steps(stepper, fused, step_args, step_kw, steps):
 
 def autotune(stepper, E, qmdt, dt, q_uniform=0.0, fused=True, steps=3, cache: Optional[str] = None,
              log=None, **kw) -> Dict[str, int]:
-    """Pick the fastest launch shape for ``stepper``'s step and apply it.
+    """Pick the fastest launch shape for ``stepper``'s step and apply it to
+    the stepper's tree (other trees keep their own knobs).
 
     Returns the chosen knob values.  With ``cache`` (a JSON path) a setting
     found earlier for the same workload signature is applied without timing,
     and new results are added to the file.
     """
     sig = signature(stepper, fused)
+    tree = stepper.tree
     if cache and os.path.exists(cache):
         with open(cache) as fh:
             known = json.load(fh)
         if sig in known:
             for k, v in known[sig]["knobs"].items():
-                tune(k, v)
+                tune(k, v, tree)
             return dict(known[sig]["knobs"])
     space = SPACES[_path(stepper, fused)]
     saved = _state(stepper)
-    base = tuning()
+    base = tuning(tree)
     args, kwargs = (E, qmdt, dt), dict(kw, q_uniform=q_uniform)
     results = []
     try:
         for combo in itertools.product(*space.values()):
             setting = dict(zip(space.keys(), combo))
             for k, v in setting.items():
-                tune(k, v)
+                tune(k, v, tree)
             _restore(stepper, saved)
             ms = _time_steps(stepper, fused, args, kwargs, steps)
             results.append((ms, setting))
@@ -98,10 +101,10 @@ def autotune(stepper, E, qmdt, dt, q_uniform=0.0, fused=True, steps=3, cache: Op
     finally:
         _restore(stepper, saved)
         for k, v in base.items():
-            tune(k, v)
+            tune(k, v, tree)
     best_ms, best = min(results, key=lambda r: r[0])
     for k, v in best.items():
-        tune(k, v)
+        tune(k, v, tree)
     if cache:
         known = {}
         if os.path.exists(cache):

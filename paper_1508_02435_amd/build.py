@@ -1,22 +1,27 @@
 """Build libpic.so (the HIP kernels and the C ABI) for gfx950 with hipcc.
 
-Run as ``python -m paper_1508_02435_amd.build``.  The library is built in
-place, next to this file, so that it travels with the source tree.
+Run as ``python -m paper_1508_02435_amd.build``.  Every source is compiled to
+an object file in parallel (the kernel sources take most of the time), then
+the objects are linked.  The library is built in place, next to this file,
+so that it travels with the source tree; objects go to ``_build/``.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_tree.hip", "pic_kernels.hip", "pic_capi.hip", "pic_profile.hip"]
+SOURCES = ["pic_tree.hip", "pic_kernels.hip", "pic_rebin.hip", "pic_rank.hip", "pic_step.hip", "pic_f32.hip",
+           "pic_stats.hip", "pic_capi.hip", "pic_profile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # the FP64 path promises the exact IEEE operation sequence: no contraction
     "-ffp-contract=off",
     # no packed FP32 instructions in device code
@@ -25,16 +30,31 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c", "-o", obj, os.path.join(CSRC, src)]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libpic.so")
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libpic.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -119,6 +119,8 @@ pic_status assemble(pic_tree *t) {
     t->o_vpinc = o; o = align256(o + (size_t)vpinc.size() * 4);
     t->o_ptab = o; o = align256(o + ptab.size() * 4);
     t->o_ctab = o; o = align256(o + ctab.size() * 4);
+    t->o_lcoord = o; o = align256(o + (size_t)NL * dim * 4);
+    t->o_pb = o; o = align256(o + (size_t)NP * dim * 4);
     t->device_bytes = (int64_t)o;
     t->image.assign(o, 0);
 
@@ -159,6 +161,8 @@ pic_status assemble(pic_tree *t) {
         put(t->image, t->o_lvtx + t->leaf_off[i] * nc * 4, lv.data(), (int64_t)lv.size());
         put(t->image, t->o_lpidt + t->leaf_off[i] * nc * 4, lp.data(), (int64_t)lp.size());
         put(t->image, t->o_plev + t->pidt_off[i], h.pidt_level.data(), (int64_t)h.pidt_level.size());
+        put(t->image, t->o_lcoord + t->leaf_off[i] * dim * 4, h.leaf_coord.data(), (int64_t)h.leaf_coord.size());
+        put(t->image, t->o_pb + t->pidt_off[i] * dim * 4, h.pidt_b.data(), (int64_t)h.pidt_b.size());
         std::vector<int32_t> idx;
         idx.assign(h.leaf_level.size(), i);
         put(t->image, t->o_linst + t->leaf_off[i] * 4, idx.data(), (int64_t)idx.size());
@@ -208,6 +212,8 @@ void bind(pic_tree *t) {
     d.vpinc = (const int32_t *)(b + t->o_vpinc);
     d.peano_tab = (const uint32_t *)(b + t->o_ptab);
     d.cell_tab = (const uint32_t *)(b + t->o_ctab);
+    d.leaf_coord = (const uint32_t *)(b + t->o_lcoord);
+    d.pidt_b = (const uint32_t *)(b + t->o_pb);
     d.status = (uint32_t *)(b + t->o_status);
 }
 
@@ -229,6 +235,74 @@ bool particles_ok(const pic_tree *t, const pic_particles *p, int precision, bool
 
 }  // namespace
 
+namespace pic {
+
+bool tune_set(Tuning &g, const char *name, int64_t value) {
+    if (!name) return false;
+    const std::string k(name);
+    auto one_of = [value](std::initializer_list<int64_t> ok) {
+        for (int64_t v : ok)
+            if (v == value) return true;
+        return false;
+    };
+    if (k == "rebin_tile") {
+        if (!one_of({2048, 4096})) return false;
+        g.rebin_ipt = (int)(value / 256);
+    } else if (k == "rebin_radix") {
+        if (!one_of({4, 5})) return false;
+        g.rebin_radix = (int)value;
+    } else if (k == "scatter_mode") {
+        if (!one_of({0, 1})) return false;
+        g.scatter_mode = (int)value;
+    } else if (k == "scatter_group") {
+        if (!one_of({1, 2, 4})) return false;
+        g.scatter_group = (int)value;
+    } else if (k == "deposit_lanes") {
+        if (!one_of({16, 32, 64})) return false;
+        g.deposit_lanes = (int)value;
+    } else if (k == "regular_tables") {
+        if (!one_of({0, 1})) return false;
+        g.regular_tables = (int)value;
+    } else if (k == "step_tile") {
+        if (!one_of({1024, 2048})) return false;
+        g.step_ipt = (int)(value / 256);
+    } else if (k == "scatter_nt") {
+        if (!one_of({0, 1})) return false;
+        g.scatter_nt = (int)value;
+    } else if (k == "xcd_tiles") {
+        if (!one_of({0, 1})) return false;
+        g.xcd_tiles = (int)value;
+    } else if (k == "deposit_bpw") {
+        if (!one_of({1, 2})) return false;
+        g.deposit_bpw = (int)value;
+    } else if (k == "emit_threads") {
+        if (!one_of({512, 1024})) return false;
+        g.emit_threads = (int)value;
+    } else {
+        return false;
+    }
+    return true;
+}
+
+int64_t tune_get(const Tuning &g, const char *name) {
+    if (!name) return -1;
+    const std::string k(name);
+    if (k == "rebin_tile") return 256 * (int64_t)g.rebin_ipt;
+    if (k == "rebin_radix") return g.rebin_radix;
+    if (k == "scatter_mode") return g.scatter_mode;
+    if (k == "scatter_nt") return g.scatter_nt;
+    if (k == "scatter_group") return g.scatter_group;
+    if (k == "deposit_lanes") return g.deposit_lanes;
+    if (k == "step_tile") return 256 * (int64_t)g.step_ipt;
+    if (k == "regular_tables") return g.regular_tables;
+    if (k == "xcd_tiles") return g.xcd_tiles;
+    if (k == "emit_threads") return g.emit_threads;
+    if (k == "deposit_bpw") return g.deposit_bpw;
+    return -1;
+}
+
+}  // namespace pic
+
 extern "C" {
 
 pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level, const uint8_t *masks,
@@ -247,6 +321,7 @@ pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level
     if (!t) return PIC_E_ARG;
     t->dim = dim;
     t->n_inst = n_inst;
+    t->tune = g_tune;
     t->inst.resize(n_inst);
     const uint8_t *m = masks;
     for (int i = 0; i < n_inst; ++i) {
@@ -428,8 +503,9 @@ size_t pic_scratch_bytes(const pic_tree *t, int64_t n, int32_t scheme, int32_t p
 pic_status pic_rebin(const pic_tree *t, int32_t scheme, int64_t n, const uint32_t *new_bin,
                      const int64_t *old_start, int32_t n_cols, void *const *cols_in, void *const *cols_out,
                      const int32_t *col_bytes, int64_t *new_start, void *scratch, size_t scratch_bytes,
-                     void *stream) {
+                     pic_rebin_stats *stats, void *stream) {
     if (!t || !valid_scheme(scheme) || n < 0 || n >= (int64_t)INT32_MAX) return PIC_E_ARG;
+    if (stats && !old_start) return PIC_E_ARG;
     if (n_cols < 0 || n_cols > 16 || !new_start || !scratch) return PIC_E_ARG;
     if (n > 0 && !new_bin) return PIC_E_ARG;
     if (n_cols > 0 && (!cols_in || !cols_out || !col_bytes)) return PIC_E_ARG;
@@ -444,6 +520,8 @@ pic_status pic_rebin(const pic_tree *t, int32_t scheme, int64_t n, const uint32_
     }
     if (scratch_bytes < rebin_scratch_bytes(t, n, scheme)) return PIC_E_SCRATCH;
     if (!t->dev) return PIC_E_STATE;
+    if (stats && launch_rebin_stats(t, scheme, old_start, new_bin, 0, n, stats, (hipStream_t)stream) != hipSuccess)
+        return PIC_E_HIP;
     return launch_rebin(t, scheme, n, new_bin, old_start, c, new_start, scratch, scratch_bytes,
                         (hipStream_t)stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
@@ -468,7 +546,8 @@ pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_pa
                     const int64_t *bin_start, const double *const *E, double qmdt, double dt,
                     const pic_push_params *params, int32_t n_extra, void *const *extra_in, void *const *extra_out,
                     const int32_t *extra_bytes, int32_t q_column, double q_uniform, pic_particles *out,
-                    int64_t *new_bin_start, double *rho, void *scratch, size_t scratch_bytes, void *stream) {
+                    int64_t *new_bin_start, double *rho, void *scratch, size_t scratch_bytes,
+                    pic_rebin_stats *stats, void *stream) {
     if (!t || !valid_scheme(scheme) || !valid_precision(t, precision) || !particles_ok(t, in, precision, true) ||
         !out)
         return PIC_E_ARG;
@@ -499,9 +578,10 @@ pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_pa
     if (!t->dev) return PIC_E_STATE;
     hipError_t e = precision == PIC_F64
                        ? launch_step(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start,
-                                     q_column, q_uniform, rho, scratch, scratch_bytes, (hipStream_t)stream)
+                                     q_column, q_uniform, rho, scratch, scratch_bytes, stats, (hipStream_t)stream)
                        : launch_step_f32(t, scheme, in, bin_start, E, qmdt, dt, params, ex, out, new_bin_start,
-                                         q_column, q_uniform, rho, scratch, scratch_bytes, (hipStream_t)stream);
+                                         q_column, q_uniform, rho, scratch, scratch_bytes, stats,
+                                         (hipStream_t)stream);
     return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
@@ -520,70 +600,19 @@ pic_status pic_convert(const pic_tree *t, int32_t scheme, int32_t to_precision, 
 }
 
 pic_status pic_tune_set(const char *name, int64_t value) {
-    if (!name) return PIC_E_ARG;
-    std::string k(name);
-    if (k == "rebin_tile") {
-        if (value != 2048 && value != 4096) return PIC_E_ARG;
-        g_tune.rebin_ipt = (int)(value / 256);
-    } else if (k == "rebin_radix") {
-        if (value != 4 && value != 5) return PIC_E_ARG;
-        g_tune.rebin_radix = (int)value;
-    } else if (k == "scatter_mode") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
-        g_tune.scatter_mode = (int)value;
-    } else if (k == "scatter_group") {
-        if (value != 1 && value != 2 && value != 4) return PIC_E_ARG;
-        g_tune.scatter_group = (int)value;
-    } else if (k == "deposit_lanes") {
-        if (value != 16 && value != 32 && value != 64) return PIC_E_ARG;
-        g_tune.deposit_lanes = (int)value;
-    } else if (k == "regular_tables") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
-        g_tune.regular_tables = (int)value;
-    } else if (k == "step_tile") {
-        if (value != 1024 && value != 2048) return PIC_E_ARG;
-        g_tune.step_ipt = (int)(value / 256);
-    } else if (k == "scatter_nt") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
-        g_tune.scatter_nt = (int)value;
-    } else if (k == "step_rank") {
-        if (value < 0 || value > 2) return PIC_E_ARG;
-        g_tune.step_rank = (int)value;
-    } else if (k == "xcd_tiles") {
-        if (value != 0 && value != 1) return PIC_E_ARG;
-        g_tune.xcd_tiles = (int)value;
-    } else if (k == "emit_stage") {
-        if (value < 0 || value > 2) return PIC_E_ARG;
-        g_tune.emit_stage = (int)value;
-    } else if (k == "deposit_bpw") {
-        if (value != 1 && value != 2) return PIC_E_ARG;
-        g_tune.deposit_bpw = (int)value;
-    } else if (k == "emit_threads") {
-        if (value != 256 && value != 512 && value != 1024) return PIC_E_ARG;
-        g_tune.emit_threads = (int)value;
-    } else {
-        return PIC_E_ARG;
-    }
-    return PIC_OK;
+    return tune_set(g_tune, name, value) ? PIC_OK : PIC_E_ARG;
 }
 
-int64_t pic_tune_get(const char *name) {
-    if (!name) return -1;
-    std::string k(name);
-    if (k == "rebin_tile") return 256 * (int64_t)g_tune.rebin_ipt;
-    if (k == "rebin_radix") return g_tune.rebin_radix;
-    if (k == "scatter_mode") return g_tune.scatter_mode;
-    if (k == "scatter_nt") return g_tune.scatter_nt;
-    if (k == "scatter_group") return g_tune.scatter_group;
-    if (k == "deposit_lanes") return g_tune.deposit_lanes;
-    if (k == "step_tile") return 256 * (int64_t)g_tune.step_ipt;
-    if (k == "regular_tables") return g_tune.regular_tables;
-    if (k == "step_rank") return g_tune.step_rank;
-    if (k == "xcd_tiles") return g_tune.xcd_tiles;
-    if (k == "emit_stage") return g_tune.emit_stage;
-    if (k == "emit_threads") return g_tune.emit_threads;
-    if (k == "deposit_bpw") return g_tune.deposit_bpw;
-    return -1;
+int64_t pic_tune_get(const char *name) { return tune_get(g_tune, name); }
+
+pic_status pic_tree_tune_set(pic_tree *t, const char *name, int64_t value) {
+    if (!t || !name || std::string(name) == "regular_tables") return PIC_E_ARG;
+    return tune_set(t->tune, name, value) ? PIC_OK : PIC_E_ARG;
+}
+
+int64_t pic_tree_tune_get(const pic_tree *t, const char *name) {
+    if (!t || !name || std::string(name) == "regular_tables") return -1;
+    return tune_get(t->tune, name);
 }
 
 pic_status pic_stream_push(int32_t dim, int64_t n, double *const *x, double *const *v, double dt, void *stream) {

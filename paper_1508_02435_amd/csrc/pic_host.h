@@ -37,6 +37,26 @@ void build_incidence(int dim, const HostInst &h, int32_t leaf_off, int32_t pidt_
                      std::vector<std::vector<int32_t>> &vpinc_rows);
 uint64_t host_peano(int dim, const uint32_t *a, int nd);
 
+// Launch-shape knobs.  Every tree carries its own set (pic_tree_tune_set),
+// copied from the process defaults (pic_tune_set) when the tree is created.
+struct Tuning {
+    int rebin_ipt = 8;      // particles per thread in a rebin tile: 8 (2048 tile) or 16 (4096 tile)
+    int rebin_radix = 4;    // bits per LDS radix pass: 4 or 5
+    int scatter_mode = 0;   // 0: LDS-staged scatter, 1: direct gather from the tile
+    int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
+    int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
+    int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
+    int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
+    int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
+    int emit_threads = 1024; // threads per emit block: 512 or 1024
+    int deposit_bpw = 1;    // bins a deposit lane group takes one after the other: 1 or 2
+    int regular_tables = 1; // build Peano rank tables for regular instances (read when a tree is created)
+};
+extern Tuning g_tune;      // process defaults for trees created afterwards
+// Knob by name: set returns false for unknown names or values; get returns -1.
+bool tune_set(Tuning &t, const char *name, int64_t value);
+int64_t tune_get(const Tuning &t, const char *name);
+
 }  // namespace pic
 
 // The opaque tree object of the C ABI.
@@ -50,11 +70,12 @@ struct pic_tree {
     // byte offsets of the tables inside the image
     int64_t o_status = 0, o_inst = 0, o_node = 0, o_ubase = 0, o_umeta = 0, o_llev = 0, o_lvtx = 0,
             o_lpidt = 0, o_plev = 0, o_linst = 0, o_pinst = 0, o_vinst = 0, o_vptr = 0, o_vinc = 0,
-            o_vpptr = 0, o_vpinc = 0, o_ptab = 0, o_ctab = 0;
+            o_vpptr = 0, o_vpinc = 0, o_ptab = 0, o_ctab = 0, o_lcoord = 0, o_pb = 0;
     int64_t n_nodes = 0, n_vinc = 0, n_vpinc = 0;
     void *dev = nullptr;               // bound device buffer (caller-owned)
     pic::DevTree dt{};                 // device view, valid once uploaded
     pic::DevInst inst0{};              // instance 0 (passed by value for single trees)
+    pic::Tuning tune{};                // launch-shape knobs of this tree
 };
 
 namespace pic {
@@ -95,23 +116,6 @@ hipError_t launch_rebin(const pic_tree *t, int scheme, int64_t n, const uint32_t
                         void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme);
 
-// Launch-shape knobs (set through pic_tune_set; read at launch time).
-struct Tuning {
-    int rebin_ipt = 8;      // particles per thread in a rebin tile: 8 (2048 tile) or 16 (4096 tile)
-    int rebin_radix = 4;    // bits per LDS radix pass: 4 or 5
-    int scatter_mode = 0;   // 0: LDS-staged scatter, 1: direct gather from the tile
-    int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
-    int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
-    int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
-    int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
-    int step_rank = 2;      // fused step: 2 = key + group + emit, 1 = rank + emit, 0 = count + move
-    int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
-    int emit_stage = 2;     // emit pass: columns staged through LDS per barrier (1 or 2), 0 = direct stores
-    int emit_threads = 1024; // threads per emit block: 256, 512 or 1024
-    int deposit_bpw = 1;    // bins a deposit lane group takes one after the other: 1 or 2
-    int regular_tables = 1; // build Peano rank tables for regular instances of trees created afterwards
-};
-extern Tuning g_tune;
 hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
                           const int64_t *bin_start, const double *q, double q_uniform, double *rho,
                           void *scratch, size_t scratch_bytes, hipStream_t s);
@@ -120,7 +124,7 @@ hipError_t launch_status_clear(const pic_tree *t, hipStream_t s);
 hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
                        const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,
                        pic_particles *out, int64_t *new_start, int q_col, double q_uniform, double *rho,
-                       void *scratch, size_t scratch_bytes, hipStream_t s);
+                       void *scratch, size_t scratch_bytes, void *stats, hipStream_t s);
 hipError_t launch_gather_push_f32(const pic_tree *t, int scheme, pic_particles *p, const double *const *E,
                                   double qmdt, double dt, const pic_push_params *pp, const int64_t *bin_start,
                                   const uint32_t *tile_bin, int tile, uint32_t *bin, hipStream_t s);
@@ -133,7 +137,11 @@ size_t step_f32_scratch_bytes(const pic_tree *t, int64_t n, int scheme);
 hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
                            const double *const *E, double qmdt, double dt, const pic_push_params *pp,
                            const Cols &extra, pic_particles *out, int64_t *new_start, int q_col, double q_uniform,
-                           double *rho, void *scratch, size_t scratch_bytes, hipStream_t s);
+                           double *rho, void *scratch, size_t scratch_bytes, void *stats, hipStream_t s);
 hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *const *v, double dt, hipStream_t s);
+// Re-bin statistics of a sorted set (old_start) whose new bins are bins[p] >> shift
+// (pic_stats.hip); adds to the caller's pic_rebin_stats record.
+hipError_t launch_rebin_stats(const pic_tree *t, int scheme, const int64_t *old_start, const uint32_t *bins,
+                              int shift, int64_t n, void *stats, hipStream_t s);
 
 }  // namespace pic

@@ -7,6 +7,7 @@
 
 #define PIC_MAX_LEVEL 18      // 3^18 < 2^29: finest coordinates fit 29 bits
 #define PIC_LDS_NODES 4096    // descent-table entries staged in LDS (16 KiB)
+#define PIC_STATS_LEVELS 20   // lift-count histogram entries of the re-bin statistics
 
 // status bits in the device status word (sticky, OR-ed by kernels)
 #define PIC_DEV_NONFINITE 1u
@@ -121,6 +122,8 @@ struct DevTree {
     const int32_t *vpinc;
     const uint32_t *peano_tab;  // per level of regular instances: Peano rank of finest cell c0 + S c1 (+ S^2 c2)
     const uint32_t *cell_tab;   // the inverse: lattice index c0 + S c1 (+ S^2 c2) of each Peano rank
+    const uint32_t *leaf_coord; // n_leaves * dim: leaf coordinates at the leaf's own level
+    const uint32_t *pidt_b;     // n_pidt * dim: vertex coordinates at the bin's level
     uint32_t *status;           // sticky device status word
 };
 

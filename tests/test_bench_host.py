@@ -26,17 +26,14 @@ def test_three_call_bytes_fp32(dim, calls):
 
 def test_fused_bytes_per_pass_form():
     """2D FP64: key pass 36, group pass 8, writing pass 68, deposit 16."""
-    ab = bench.algorithmic_bytes(2, False, 2)
+    ab = bench.algorithmic_bytes(2, False)
     assert (ab["step_key"], ab["step_group"], ab["step_emit"], ab["deposit_bins"]) == (36, 8, 68, 16)
     assert ab["fused"] == 128
-    assert bench.algorithmic_bytes(2, False, 1)["fused"] == 36 + 68 + 16
-    assert bench.algorithmic_bytes(2, False, 0)["fused"] == 32 + 64 + 16
-    # every pass form moves fewer bytes than the three calls
-    for r in (0, 1, 2):
-        for dim in (2, 3):
-            for q in (False, True):
-                ab = bench.algorithmic_bytes(dim, q, r)
-                assert ab["fused"] < ab["calls"]
+    # the fused step moves fewer bytes than the three calls
+    for dim in (2, 3):
+        for q in (False, True):
+            ab = bench.algorithmic_bytes(dim, q)
+            assert ab["fused"] < ab["calls"]
 
 
 def test_more_than_one_gpu_is_refused():

@@ -94,7 +94,7 @@ def test_autotune_changes_speed_not_results(fused, tmp_path):
         cache = str(tmp_path / "tune.json")
         best = autotune.autotune(st, E, 0.0, 0.0, fused=fused, steps=1, cache=cache, **kw)
         assert set(best) == set(autotune.SPACES["fused_f64" if fused else "calls_f64"])
-        assert all(pic.tuning()[k] == v for k, v in best.items())
+        assert all(pic.tuning(t)[k] == v for k, v in best.items())
         # the tuner restored the state it timed on; one step now equals the reference
         (st.step_fused if fused else st.step)(E, 0.0, 0.0, **kw)
         torch.cuda.synchronize()
@@ -102,8 +102,10 @@ def test_autotune_changes_speed_not_results(fused, tmp_path):
             assert np.array_equal(a, b)
         # a cached signature applies without timing
         for k, val in before.items():
-            pic.tune(k, val)
+            if k not in pic.PROCESS_ONLY:
+                pic.tune(k, val, t)
         assert autotune.autotune(st, E, 0.0, 0.0, fused=fused, cache=cache, **kw) == best
+        assert all(pic.tuning(t)[k] == v for k, v in best.items())
     finally:
         for k, val in before.items():
             pic.tune(k, val)

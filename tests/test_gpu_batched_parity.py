@@ -1,0 +1,157 @@
+"""GPU parity of the batched form against the oracle, instance by instance.
+
+The batched step runs the forest kernels (one launch per pass over every
+instance, per-instance (q/m) dt and dt read from device arrays), eagerly and
+replayed from a HIP graph.  Each instance of the forest must give exactly
+what the oracle gives for that instance alone as a single tree: bin offsets,
+order (particle tags), positions and velocities bit for bit, vertex charge
+within 1e-12 relative per vertex (FP64); the FP32 form within its stated
+per-quantity bounds.  Instances follow the batched workload's recipe (depths
+3-5 mixed, log-uniform sizes, Langmuir parameters per instance) at a reduced
+particle count; the full-size forest is stepped once in test_gpu_fullsize.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from f32_bounds import check_rho_f32
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1508_02435_amd as pic  # noqa: E402
+
+RHO_TOL = 1e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda")
+
+
+class Forest:
+    """The batched inputs and, per instance, the oracle's tree and state."""
+
+    def __init__(self, dev, scheme, n_inst=64, scale=0.02):
+        self.insts = W.config5(n_inst=n_inst, scale=scale)
+        assert {w.tree.max_level for w in self.insts} == {3, 4, 5}
+        self.scheme = scheme
+        self.tree = pic.Tree([w.tree for w in self.insts]).upload(dev)
+        self.counts = [w.n for w in self.insts]
+        self.p0 = np.concatenate([[0], np.cumsum(self.counts)])
+        self.inst_start = torch.tensor(self.p0, dtype=torch.int64, device=dev)
+        self.orc = [oracle.OracleTree(w.tree) for w in self.insts]
+        self.E_np = [w.field(o.vertex_positions_unit()) for w, o in zip(self.insts, self.orc)]
+        self.E = torch.tensor(np.concatenate(self.E_np, axis=1), dtype=torch.float64, device=dev)
+        self.qd = torch.tensor([w.qm * w.dt for w in self.insts], dtype=torch.float64, device=dev)
+        self.dd = torch.tensor([w.dt for w in self.insts], dtype=torch.float64, device=dev)
+        self.q_uniform = -1.0 / sum(self.counts)
+        self.x = np.concatenate([w.x for w in self.insts], axis=1)
+        self.v = np.concatenate([w.v for w in self.insts], axis=1)
+        self.ids = np.arange(self.x.shape[1], dtype=np.int64)
+        # oracle: per instance, the initial sort, then steps on demand
+        self.state = []
+        for i, (w, o) in enumerate(zip(self.insts, self.orc)):
+            xs, vs, _, start, perm = oracle.initial_sort(o, w.x, w.v, None, scheme)
+            self.state.append(dict(x=xs, v=vs, start=start, ids=perm + self.p0[i]))
+
+    def oracle_step(self):
+        for i, (w, o) in enumerate(zip(self.insts, self.orc)):
+            s = self.state[i]
+            r = oracle.step(o, s["x"], s["v"], self.E_np[i], w.qm * w.dt, w.dt, s["start"], self.scheme, None,
+                            self.q_uniform)
+            s.update(x=r["x"], v=r["v"], start=r["bin_start"], ids=s["ids"][r["perm"]], rho=r["rho"])
+
+    def bin_offset(self, i):
+        ii = self.tree.instance(i)
+        return ii.leaf_offset if self.scheme == pic.PIT else ii.pidt_offset
+
+    def check_f64(self, st, with_rho=True):
+        x, v, ids, start = (a.cpu().numpy() for a in (st.x, st.v, st.ids, st.start))
+        rho = st.rho.cpu().numpy()
+        for i, s in enumerate(self.state):
+            sl = slice(self.p0[i], self.p0[i + 1])
+            b0, nb = self.bin_offset(i), self.orc[i].n_bins(self.scheme)
+            assert np.array_equal(start[b0:b0 + nb + 1] - self.p0[i], s["start"]), f"offsets of instance {i}"
+            assert np.array_equal(ids[sl], s["ids"]), f"order of instance {i}"
+            assert np.array_equal(x[:, sl], s["x"]) and np.array_equal(v[:, sl], s["v"]), f"state of instance {i}"
+            if with_rho:
+                ii = self.tree.instance(i)
+                r = rho[ii.vertex_offset:ii.vertex_offset + ii.n_vertices]
+                err = np.abs(r - s["rho"])
+                assert (err <= RHO_TOL * np.abs(s["rho"]) + 1e-300).all(), f"charge of instance {i}"
+
+
+@pytest.mark.parametrize("scheme", [pic.PIT, pic.PIDT])
+def test_forest_fused_steps_match_oracle_per_instance(scheme):
+    dev = _dev()
+    f = Forest(dev, scheme)
+    st = pic.Stepper(f.tree, scheme, f.x, f.v, ids=f.ids, inst_start=f.inst_start, device=dev)
+    st.initial_sort()
+    torch.cuda.synchronize()
+    f.check_f64(st, with_rho=False)
+    kw = dict(q_uniform=f.q_uniform, qmdt_dev=f.qd, dt_dev=f.dd)
+    for it in range(2):
+        st.step_fused(f.E, 0.0, 0.0, **kw)
+        f.oracle_step()
+        torch.cuda.synchronize()
+        f.check_f64(st)
+    assert f.tree.status_sync() == 0
+
+
+@pytest.mark.parametrize("scheme", [pic.PIT, pic.PIDT])
+def test_forest_graph_replays_match_oracle_per_instance(scheme):
+    """StepGraph runs two eager steps while it captures, then every replay
+    runs two more: after the capture and after each of two replays the
+    forest equals the oracle run for as many steps."""
+    dev = _dev()
+    f = Forest(dev, scheme)
+    st = pic.Stepper(f.tree, scheme, f.x, f.v, ids=f.ids, inst_start=f.inst_start, device=dev)
+    st.initial_sort()
+    g = pic.StepGraph(st, f.E, 0.0, 0.0, q_uniform=f.q_uniform, qmdt_dev=f.qd, dt_dev=f.dd)
+    for rep in range(3):
+        if rep:
+            g.replay()
+        f.oracle_step()
+        f.oracle_step()
+        torch.cuda.synchronize()
+        f.check_f64(st)
+    assert f.tree.status_sync() == 0
+
+
+POS_TOL = 1e-5   # cells
+VEL_TOL = 1e-6   # relative to the instance's max |v|
+
+
+@pytest.mark.parametrize("scheme", [pic.PIT, pic.PIDT])
+def test_forest_f32_step_error_against_oracle_per_instance(scheme):
+    """The FP32 batched step (per-instance dt scaling of the offsets) against
+    the FP64 oracle, instance by instance, within the FP32 form's bounds."""
+    dev = _dev()
+    f = Forest(dev, scheme, n_inst=24)
+    xs = np.concatenate([s["x"] for s in f.state], axis=1)
+    vs = np.concatenate([s["v"] for s in f.state], axis=1)
+    ids = np.concatenate([s["ids"] for s in f.state])
+    st = pic.Stepper32(f.tree, scheme, xs, vs, ids=ids, inst_start=f.inst_start, dt_dev=f.dd, device=dev)
+    st.step_fused(f.E, 0.0, 0.0, q_uniform=f.q_uniform, qmdt_dev=f.qd, dt_dev=f.dd)
+    f.oracle_step()
+    x32, v32 = (a.cpu().numpy() for a in st.to_f64())
+    g_ids = st.ids.cpu().numpy()
+    rho = st.rho.cpu().numpy()
+    torch.cuda.synchronize()
+    assert f.tree.status_sync() == 0
+    for i, (w, s) in enumerate(zip(f.insts, f.state)):
+        sl = slice(f.p0[i], f.p0[i + 1])
+        assert set(g_ids[sl]) == set(s["ids"]), f"instance {i} lost or gained particles"
+        pos = {p: j for j, p in enumerate(s["ids"])}
+        j = np.array([pos[p] for p in g_ids[sl]])
+        S = float(3 ** w.tree.max_level)
+        dx = np.abs(x32[:, sl] - s["x"][:, j])
+        dx = np.minimum(dx, 1.0 - dx) * S
+        assert dx.max() <= POS_TOL, (i, dx.max())
+        assert np.abs(v32[:, sl] - s["v"][:, j]).max() <= VEL_TOL * np.abs(s["v"]).max(), i
+        ii = f.tree.instance(i)
+        r32 = rho[ii.vertex_offset:ii.vertex_offset + ii.n_vertices]
+        check_rho_f32(f.orc[i], s["x"], None, f.q_uniform, r32, s["rho"], f"instance {i}")

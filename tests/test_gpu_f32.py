@@ -8,9 +8,13 @@ per quantity, for one teacher-forced step from the oracle's sorted FP64 state
   bins       every particle whose FP32 bin differs from the FP64 one lies
              within the position bound of a cell face (PIT) or of a dual-cell
              face (PIDT); all others keep the FP64 order inside their bin;
-  charge     max_v |rho32 - rho64| / max_v |rho64| <= 1e-6 (vertex charge,
-             norm-wise: a vertex touched only by the far tip of a weight has a
-             tiny charge whose relative error says nothing).
+  charge     per vertex: |rho32 - rho64| / |rho64| <= 1e-6 on every populated
+             vertex (charge >= 1% of the largest; in these uniform plasmas
+             that is every vertex), and on every vertex an error <= 1e-6 times
+             the total |charge| of the particles whose leaf has it as a corner
+             (a vertex reached only by the tip of a weight holds a tiny charge
+             whose relative error says nothing); the norm-wise figure
+             max_v |rho32 - rho64| / max_v |rho64| stays below 1e-6 too.
 The FP32 fused call and the three FP32 calls must agree bit for bit.
 """
 import numpy as np
@@ -18,6 +22,7 @@ import pytest
 
 import oracle
 import workloads as W
+from f32_bounds import check_rho_f32
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -60,6 +65,12 @@ def test_f32_step_error_against_oracle(name, scheme):
     wl, o, t, xs, vs, qs, start, E = _setup(name, scheme, dev, rng)
     S = float(3 ** wl.tree.max_level)
     st = pic.Stepper32(t, scheme, xs, vs, dt=wl.dt, q=qs, ids=np.arange(wl.n), device=dev)
+    # the conversion to offsets can round a particle on a face into the next
+    # cell; such particles start in another bin than in FP64
+    b64_0 = np.repeat(np.arange(len(start) - 1), np.diff(start))
+    b32_0 = np.repeat(np.arange(len(st.start) - 1), np.diff(st.start.cpu().numpy()))
+    ids0 = st.ids.cpu().numpy()
+    moved0 = ids0[b32_0 != b64_0[ids0]]
     st.step(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform)
     r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
     torch.cuda.synchronize()
@@ -82,15 +93,18 @@ def test_f32_step_error_against_oracle(name, scheme):
         d = _face_distance(x64[:, ids[diff]] * S, scheme)
         assert d.max() <= POS_TOL, (int(diff.sum()), d.max())
     assert diff.mean() < 1e-3
-    # order: particles that agree on the bin keep the FP64 relative order
+    # order: the particles whose old and new bins agree with FP64 have the same
+    # keys (bin, stayed) in both forms, so they keep the FP64 relative order
+    diff |= np.isin(ids, moved0)
     rank64 = np.empty(wl.n, dtype=np.int64)
     rank64[r["perm"]] = np.arange(wl.n)
     keep = ~diff
     rk = rank64[ids[keep]]
     same_bin = b32[keep][1:] == b32[keep][:-1]
-    assert (np.diff(rk)[same_bin] > 0).all() or diff.any()
+    assert (np.diff(rk)[same_bin] > 0).all()
     rho32, rho64 = st.rho.cpu().numpy(), r["rho"]
     assert np.abs(rho32 - rho64).max() <= RHO_TOL * np.abs(rho64).max()
+    check_rho_f32(o, r["x"], r["q"], wl.q_uniform, rho32, rho64, name)
 
 
 @pytest.mark.parametrize("name,scheme", CASES)
@@ -182,4 +196,29 @@ def test_f32_charge_is_conserved_over_steps():
         total = st.rho.sum().item()
         assert abs(total - wl.q_uniform * wl.n) <= 1e-6 * abs(wl.q_uniform * wl.n)
     assert int(st.start[-1].item()) == wl.n
+    assert t.status_sync() == 0
+
+
+@pytest.mark.parametrize("name,scheme", CASES)
+def test_f32_rebin_stats(name, scheme):
+    """The FP32 fused call and the three FP32 calls count the same movers and
+    lifts; against the FP64 oracle they differ only by particles whose FP32
+    bin differs (particles within the position bound of a face)."""
+    dev = _dev()
+    rng = np.random.default_rng(13)
+    wl, o, t, xs, vs, qs, start, E = _setup(name, scheme, dev, rng)
+    Ed = torch.tensor(E, device=dev)
+    got = []
+    for fused in (False, True):
+        st = pic.Stepper32(t, scheme, xs, vs, dt=wl.dt, q=qs, device=dev)
+        stats = pic.new_stats(dev)
+        (st.step_fused if fused else st.step)(Ed, wl.qm * wl.dt, wl.dt, q_uniform=wl.q_uniform, stats=stats)
+        torch.cuda.synchronize()
+        got.append(pic.read_stats(stats))
+    assert got[0] == got[1]
+    r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+    want = o.rebin_stats(start, r["new_bin"], scheme)
+    assert got[0]["particles"] == want["particles"]
+    assert abs(got[0]["movers"] - want["movers"]) <= 1e-3 * wl.n
+    assert abs(got[0]["lifts"] - want["lifts"]) <= 1e-3 * wl.n * wl.tree.max_level
     assert t.status_sync() == 0

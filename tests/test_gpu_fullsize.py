@@ -1,0 +1,144 @@
+"""Full-size GPU parity: one teacher-forced step of the benchmark workloads.
+
+The benchmark times pic_step with the default launch shape on the full
+particle sets.  These tests run that same call on the same generated inputs
+(the sorted initial state and the first step's field) and compare the whole
+result with the oracle: the initial sort (offsets and positions), then after
+one step the bin offsets, positions and velocities bit for bit (so the order
+too, positions being distinct) and the vertex charge within 1e-12 relative
+per vertex (paper Sec. 5.1 Theorem 1, Sec. 5.2 Theorem 2, Sec. 3 step 1).
+
+At these sizes the step exercises what the small cases cannot: thousands of
+tiles, dozens of look-back scan blocks, keys collecting 60-130 runs, and
+(config 4) the 3D kernels at 34M particles.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1508_02435_amd as pic  # noqa: E402
+
+RHO_TOL = 1e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda")
+
+
+def _eq(a_dev, b, what):
+    a = a_dev.cpu().numpy()
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{what}: {len(bad)} entries differ, first at {bad[0].tolist()}")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name,scheme", [("config2", pic.PIT), ("config2", pic.PIDT), ("config3", pic.PIT),
+                                         ("config4", pic.PIT)])
+def test_benchmark_step_matches_oracle_at_full_size(name, scheme):
+    dev = _dev()
+    print(f"[fullsize] {name} scheme {scheme}", flush=True)
+    wl = W.by_name(name)
+    o = oracle.OracleTree(wl.tree)
+    t = pic.Tree(wl.tree).upload(dev)
+    E_np = wl.field(o.vertex_positions_unit())
+    st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, device=dev)
+    st.initial_sort()
+    xs, vs, qs, start, _ = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+    torch.cuda.synchronize()
+    _eq(st.start, start, "initial offsets")
+    _eq(st.x, xs, "initially sorted positions")
+    qm, dt, q_uniform = wl.qm, wl.dt, wl.q_uniform
+    del wl
+    gc.collect()
+    E = torch.tensor(E_np, dtype=torch.float64, device=dev)
+    st.step_fused(E, qm * dt, dt, q_uniform=q_uniform)
+    r = oracle.step(o, xs, vs, E_np, qm * dt, dt, start, scheme, qs, q_uniform)
+    del xs, vs
+    torch.cuda.synchronize()
+    assert t.status_sync() == 0
+    _eq(st.start, r["bin_start"], "bin offsets after the step")
+    _eq(st.x, r["x"], "positions after the step")
+    _eq(st.v, r["v"], "velocities after the step")
+    if qs is not None:
+        _eq(st.q, r["q"], "charges after the step")
+    rho, rho_o = st.rho.cpu().numpy(), r["rho"]
+    err = np.abs(rho - rho_o)
+    ok = err <= RHO_TOL * np.abs(rho_o) + 1e-300
+    assert ok.all(), (float(err.max()), int((~ok).sum()))
+
+
+@pytest.mark.timeout(600)
+def test_batched_forest_matches_oracle_at_full_size():
+    """The full batched workload (64 instances, depths 3-5, 72.7M particles)
+    stepped as the benchmark steps it: a StepGraph (whose capture runs two
+    eager steps) and one replay (two more).  After the capture every
+    instance equals the oracle's two steps of that instance as a single
+    tree; after the replay a sample of eight instances (every depth, the
+    largest ones among them) equals the oracle's four steps."""
+    dev = _dev()
+    insts = W.config5()
+    p0 = np.concatenate([[0], np.cumsum([w.n for w in insts])])
+    print(f"[fullsize] config5 {len(insts)} instances, {p0[-1]} particles", flush=True)
+    t = pic.Tree([w.tree for w in insts]).upload(dev)
+    orc = [oracle.OracleTree(w.tree) for w in insts]
+    E_np = [w.field(o.vertex_positions_unit()) for w, o in zip(insts, orc)]
+    E = torch.tensor(np.concatenate(E_np, axis=1), dtype=torch.float64, device=dev)
+    qd = torch.tensor([w.qm * w.dt for w in insts], dtype=torch.float64, device=dev)
+    dd = torch.tensor([w.dt for w in insts], dtype=torch.float64, device=dev)
+    q_uniform = -1.0 / int(p0[-1])
+    inst_start = torch.tensor(p0, dtype=torch.int64, device=dev)
+    st = pic.Stepper(t, pic.PIT, np.concatenate([w.x for w in insts], axis=1),
+                     np.concatenate([w.v for w in insts], axis=1), inst_start=inst_start, device=dev)
+    st.initial_sort()
+    g = pic.StepGraph(st, E, 0.0, 0.0, q_uniform=q_uniform, qmdt_dev=qd, dt_dev=dd)
+    torch.cuda.synchronize()
+    state = []
+    levels = np.array([w.tree.max_level for w in insts])
+    sizes = np.array([w.n for w in insts])
+    for i, (w, o) in enumerate(zip(insts, orc)):
+        xs, vs, _, start, _ = oracle.initial_sort(o, w.x, w.v, None, pic.PIT)
+        state.append(dict(x=xs, v=vs, start=start))
+        w.x = w.v = None
+
+    def advance(i, steps):
+        w, s = insts[i], state[i]
+        for _ in range(steps):
+            r = oracle.step(orc[i], s["x"], s["v"], E_np[i], w.qm * w.dt, w.dt, s["start"], pic.PIT, None, q_uniform)
+            s.update(x=r["x"], v=r["v"], start=r["bin_start"], rho=r["rho"])
+
+    def check(i, x, v, start, rho):
+        ii = t.instance(i)
+        s = state[i]
+        sl = slice(p0[i], p0[i + 1])
+        b0 = ii.leaf_offset
+        assert np.array_equal(start[b0:b0 + ii.n_leaves + 1] - p0[i], s["start"]), f"offsets of instance {i}"
+        assert np.array_equal(x[:, sl], s["x"]) and np.array_equal(v[:, sl], s["v"]), f"state of instance {i}"
+        r = rho[ii.vertex_offset:ii.vertex_offset + ii.n_vertices]
+        assert (np.abs(r - s["rho"]) <= RHO_TOL * np.abs(s["rho"]) + 1e-300).all(), f"charge of instance {i}"
+
+    x, v, start, rho = (a.cpu().numpy() for a in (st.x, st.v, st.start, st.rho))
+    for i in range(len(insts)):
+        advance(i, 2)
+        check(i, x, v, start, rho)
+    g.replay()
+    torch.cuda.synchronize()
+    x, v, start, rho = (a.cpu().numpy() for a in (st.x, st.v, st.start, st.rho))
+    sample = set()
+    for L in (3, 4, 5):
+        idx = np.flatnonzero(levels == L)
+        sample.update(idx[np.argsort(-sizes[idx])[:2]].tolist())
+    sample.update(np.argsort(-sizes)[:8 - len(sample)].tolist())
+    for i in sorted(sample):
+        advance(i, 2)
+        check(i, x, v, start, rho)
+    assert t.status_sync() == 0

@@ -312,9 +312,8 @@ def test_fused_step_matches_oracle(name, scheme, kind):
     assert t.status_sync() == 0
 
 
-STEP_FORMS = [dict(step_rank=r, emit_stage=st, emit_threads=nt, xcd_tiles=x, step_tile=tl)
-              for r in (2, 1) for st in (1, 2, 0) for nt in (1024, 512, 256) for x in (1, 0) for tl in (2048,)]
-STEP_FORMS += [dict(step_rank=r, step_tile=1024) for r in (2, 1, 0)] + [dict(step_rank=0, step_tile=2048)]
+STEP_FORMS = [dict(emit_threads=nt, xcd_tiles=x, step_tile=tl) for nt in (1024, 512) for x in (1, 0)
+              for tl in (2048, 1024)]
 
 
 @pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
@@ -352,9 +351,9 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
 
 
 @pytest.mark.parametrize("tiles", [80, 160])
-@pytest.mark.parametrize("step_rank", [2, 1])
+@pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_fused_step_with_overfull_key_lists(step_rank, scheme, tiles):
+def test_fused_step_with_overfull_key_lists(step_tile, scheme, tiles):
     """Every tile sends particles to every bin of a 3x3 tree, so each key
     collects about as many runs as there are tiles: 80 take the placement by
     counting (more than a wavefront sorts), 160 overflow the direct list into
@@ -362,7 +361,7 @@ def test_fused_step_with_overfull_key_lists(step_rank, scheme, tiles):
     dev = _dev()
     saved = pic.tuning()
     try:
-        pic.tune("step_rank", step_rank)
+        pic.tune("step_tile", step_tile)
         rng = np.random.default_rng(31)
         spec = W.regular_tree(2, 1)
         n = tiles * 2048 + 77
@@ -386,8 +385,7 @@ def test_fused_step_with_overfull_key_lists(step_rank, scheme, tiles):
             pic.tune(k, v)
 
 
-MANY_RUN_FORMS = [dict(), dict(emit_stage=0), dict(emit_stage=1), dict(emit_stage=2, emit_threads=256),
-                  dict(step_rank=1), dict(step_tile=1024, emit_threads=512)]
+MANY_RUN_FORMS = [dict(), dict(emit_threads=512), dict(step_tile=1024), dict(step_tile=1024, emit_threads=512)]
 
 
 @pytest.mark.parametrize("knobs", MANY_RUN_FORMS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()) or "default")
@@ -496,3 +494,77 @@ def test_regular_tree_without_tables_matches_oracle(name, scheme):
         _check_rho(st.rho.cpu().numpy(), r["rho"])
         xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
     assert t.status_sync() == 0
+
+
+def _add_stats(acc, st):
+    if acc is None:
+        return dict(st, lift_hist=list(st["lift_hist"]))
+    for k in ("particles", "movers", "lifts"):
+        acc[k] += st[k]
+    acc["max_tunnel"] = max(acc["max_tunnel"], st["max_tunnel"])
+    acc["lift_hist"] = [a + b for a, b in zip(acc["lift_hist"], st["lift_hist"])]
+    return acc
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("name,scheme", CASES)
+def test_rebin_stats_match_oracle(name, scheme, fused):
+    """Re-bin statistics (movers, lifts per particle, the lift-count
+    histogram and the largest tunnel distance, paper Sec. 6.1) of pic_rebin
+    and of pic_step, accumulated over three teacher-forced steps with
+    tunnelling fields, equal the oracle's bit for bit."""
+    dev = _dev()
+    wl = W.by_name(name)
+    o = oracle.OracleTree(wl.tree)
+    t = _tree(wl.tree)
+    rng = np.random.default_rng(61)
+    st = pic.Stepper(t, scheme, wl.x, wl.v, q=wl.q, device=dev)
+    st.initial_sort()
+    xs, vs, qs, start, _ = oracle.initial_sort(o, wl.x, wl.v, wl.q, scheme)
+    stats = pic.new_stats(dev)
+    want = None
+    for it in range(3):
+        E = _field(o, wl, rng, "random")
+        st.x.copy_(torch.from_numpy(xs))
+        st.v.copy_(torch.from_numpy(vs))
+        (st.step_fused if fused else st.step)(torch.tensor(E, device=dev), wl.qm * wl.dt, wl.dt,
+                                              q_uniform=wl.q_uniform, stats=stats)
+        r = oracle.step(o, xs, vs, E, wl.qm * wl.dt, wl.dt, start, scheme, qs, wl.q_uniform)
+        want = _add_stats(want, o.rebin_stats(start, r["new_bin"], scheme))
+        xs, vs, qs, start = r["x"], r["v"], r["q"], r["bin_start"]
+    torch.cuda.synchronize()
+    got = pic.read_stats(stats)
+    assert want["movers"] > 0 and max(i for i, c in enumerate(want["lift_hist"]) if c) >= 2
+    assert got == want
+    assert t.status_sync() == 0
+
+
+def test_forest_stats_match_oracle_per_instance_sum():
+    """A forest's statistics are the sums (and the largest tunnel) of its
+    instances' statistics taken one by one by the oracle."""
+    dev = _dev()
+    insts = W.config5(n_inst=6, n_min=2e3, n_max=3e4)
+    t = _tree([w.tree for w in insts])
+    counts = [w.n for w in insts]
+    inst_start = torch.tensor(np.concatenate([[0], np.cumsum(counts)]), dtype=torch.int64, device=dev)
+    orc = [oracle.OracleTree(w.tree) for w in insts]
+    rng = np.random.default_rng(8)
+    Es = [W.random_field(rng, 2, o.n_vertices, 2.0 * w.h / w.dt ** 2) for w, o in zip(insts, orc)]
+    E = torch.tensor(np.concatenate(Es, axis=1), device=dev)
+    qd = torch.tensor([w.qm * w.dt for w in insts], dtype=torch.float64, device=dev)
+    dd = torch.tensor([w.dt for w in insts], dtype=torch.float64, device=dev)
+    for scheme in (0, 1):
+        x = np.concatenate([w.x for w in insts], axis=1)
+        v = np.concatenate([w.v for w in insts], axis=1)
+        st = pic.Stepper(t, scheme, x, v, inst_start=inst_start, device=dev)
+        st.initial_sort()
+        stats = pic.new_stats(dev)
+        st.step_fused(E, 0.0, 0.0, q_uniform=-1.0, qmdt_dev=qd, dt_dev=dd, stats=stats)
+        want = None
+        for i, (w, o) in enumerate(zip(insts, orc)):
+            xs, vs, _, start, _ = oracle.initial_sort(o, w.x, w.v, None, scheme)
+            r = oracle.step(o, xs, vs, Es[i], w.qm * w.dt, w.dt, start, scheme, None, -1.0)
+            want = _add_stats(want, o.rebin_stats(start, r["new_bin"], scheme))
+        torch.cuda.synchronize()
+        assert pic.read_stats(stats) == want
+        assert t.status_sync() == 0

@@ -124,16 +124,21 @@ def test_calls_check_arguments_before_the_device():
     fake = C.c_void_p(0x1000)
     start = C.c_void_p(0x2000)
     nb = C.c_void_p(0x3000)
-    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 0, None, None, None, start, fake, need - 1, None) \
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 0, None, None, None, start, fake, need - 1, None, None) \
         == _capi.PIC_E_SCRATCH
+    # statistics need the old offsets (a sorted input)
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 0, None, None, None, start, fake, need, C.c_void_p(0x6000),
+                       None) == _capi.PIC_E_ARG
     # bad column width
     cols = (C.c_void_p * 1)(0x4000)
     outs = (C.c_void_p * 1)(0x5000)
     w = (C.c_int32 * 1)(2)
-    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, outs, w, start, fake, need, None) == _capi.PIC_E_ARG
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, outs, w, start, fake, need, None, None) \
+        == _capi.PIC_E_ARG
     # aliasing columns
     w8 = (C.c_int32 * 1)(8)
-    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, cols, w8, start, fake, need, None) == _capi.PIC_E_ARG
+    assert L.pic_rebin(t.handle, 0, 1000, nb, None, 1, cols, cols, w8, start, fake, need, None, None) \
+        == _capi.PIC_E_ARG
     assert L.pic_status_sync(t.handle, None) == _capi.PIC_E_STATE
     assert _capi.status_string(_capi.PIC_E_SCRATCH) == "scratch buffer too small"
 
@@ -150,6 +155,29 @@ def test_tuning_knobs_accept_only_listed_values():
         with pytest.raises(pic.PicError):
             pic.tune("no_such_knob", 1)
         assert _capi.lib().pic_tune_get(b"no_such_knob") == -1
+    finally:
+        for k, v in before.items():
+            pic.tune(k, v)
+
+
+def test_knobs_are_per_tree():
+    """A tree copies the process defaults when it is created; changing one
+    tree's knobs changes neither the defaults nor another tree's."""
+    before = pic.tuning()
+    try:
+        pic.tune("step_tile", 1024)
+        a = pic.Tree(W.regular_tree(2, 2))
+        pic.tune("step_tile", 2048)
+        b = pic.Tree(W.regular_tree(2, 2))
+        assert pic.tuning(a)["step_tile"] == 1024 and pic.tuning(b)["step_tile"] == 2048
+        pic.tune("emit_threads", 512, a)
+        assert pic.tuning(a)["emit_threads"] == 512
+        assert pic.tuning(b)["emit_threads"] == pic.tuning()["emit_threads"] == before["emit_threads"]
+        with pytest.raises(pic.PicError):
+            pic.tune("emit_threads", 256, a)
+        with pytest.raises(pic.PicError):                 # read only when a tree is created
+            pic.tune("regular_tables", 0, a)
+        assert "regular_tables" not in pic.tuning(a)
     finally:
         for k, v in before.items():
             pic.tune(k, v)

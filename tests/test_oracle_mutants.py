@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as P
+import test_oracle_stats as ST
 import workloads as W
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pic_oracle.c")
@@ -50,6 +51,9 @@ MUTANTS = {
                                "uint64_t span = (uint64_t)ipow3(t->L - n->level);"),
     "vertex_order_axis1_fastest": ("for (int k = 0; k < dim; ++k) { r += a[k] * m; m *= n; }",
                                    "for (int k = dim - 1; k >= 0; --k) { r += a[k] * m; m *= n; }"),
+    "stats_lifts_from_new_level": ("const int lifts = l0 - m;", "const int lifts = l1 - m;"),
+    "stats_dual_cells_unshifted": ("a[k] = (bk + (nl - 1) / 2) % nl;", "a[k] = bk % nl;"),
+    "stats_tunnel_not_periodic": ("if (t->S - d < d) d = t->S - d;", ""),
 }
 
 # fast pins, cheapest first; a mutant must make at least one of them fail
@@ -69,6 +73,9 @@ PINS = [
     lambda: P.test_locate_matches_brute_force(W.disc_tree(2, 2, 4)),
     lambda: P.test_step_satisfies_theorems_and_order("small_adaptive", 0),
     lambda: P.test_step_satisfies_theorems_and_order("small_adaptive", 1),
+    lambda: ST.test_hand_computed_lifts_on_a_9x9_tree(),
+    lambda: ST.test_stats_match_the_lift_mechanism("disc2d_1_3", oracle.PIT, 4),
+    lambda: ST.test_stats_match_the_lift_mechanism("reg2d_L2", oracle.PIDT, 4),
 ]
 
 
