@@ -229,6 +229,28 @@ pic_status pic_gather_push(const pic_tree *tree, int32_t scheme, int32_t precisi
 size_t pic_scratch_bytes(const pic_tree *tree, int64_t n, int32_t scheme, int32_t precision);
 
 /*
+ * The deposit above for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and result as pic_deposit (the same kernels in
+ * the same order, so rho is bit-identical), without the scratch argument:
+ * the per-bin partials live in a device-resident array of
+ * PIC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  The call allocates nothing (no hipMalloc, no
+ * hipFree; kernel timing is off during it).  Limit: the partials take
+ * n_bins * 8 * (2^dim for PIT, 3^dim for PIDT) bytes; trees needing more than
+ * PIC_NOALLOC_SCRATCH_BYTES get PIC_E_SCRATCH (every 2D tree up to depth 6,
+ * 3D PIT trees up to depth 4 and 3D PIDT trees up to depth 3 fit).  The array is looked up for the device that
+ * is current at the call; `stream` must belong to it.  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other host threads) race; calls ordered on one stream do not.  Nothing in
+ * the array needs to start at zero: each call writes every partial it reads.
+ */
+#define PIC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pic_status pic_deposit_noalloc(const pic_tree *tree, int32_t scheme, int32_t precision,
+                               const pic_particles *p, const int64_t *bin_start_dev, const double *q_dev,
+                               double q_uniform, double *rho_dev, void *stream);
+
+/*
  * Re-bin statistics (paper Sec. 6.1: lifts per particle and time step).  In
  * the paper's PIT a particle that leaves its leaf is lifted towards the root
  * until a cell covers it and dropped from there into its new leaf, so a

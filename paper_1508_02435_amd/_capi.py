@@ -18,8 +18,9 @@ EXPORTS = [
     "pic_status_sync", "pic_status_string", "pic_locate", "pic_gather_push", "pic_scratch_bytes",
     "pic_rebin", "pic_deposit", "pic_stream_push", "pic_profile_enable", "pic_profile_read",
     "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only", "pic_convert",
-    "pic_tree_tune_set", "pic_tree_tune_get",
+    "pic_tree_tune_set", "pic_tree_tune_get", "pic_deposit_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PIC_NOALLOC_SCRATCH_BYTES
 
 STATS_LEVELS = 20          # PIC_STATS_LEVELS
 STATS_WORDS = 4 + STATS_LEVELS   # pic_rebin_stats: particles, movers, lifts, max_tunnel, lift_hist[]
@@ -99,6 +100,8 @@ def lib():
         L.pic_rebin.restype = i32
         L.pic_deposit.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, vp, vp, sz, vp]
         L.pic_deposit.restype = i32
+        L.pic_deposit_noalloc.argtypes = [vp, i32, i32, C.POINTER(Particles), vp, vp, dbl, vp, vp]
+        L.pic_deposit_noalloc.restype = i32
         L.pic_stream_push.argtypes = [i32, i64, vp, vp, dbl, vp]
         L.pic_stream_push.restype = i32
         L.pic_profile_enable.argtypes = [i32]

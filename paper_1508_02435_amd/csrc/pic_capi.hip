@@ -542,6 +542,25 @@ pic_status pic_deposit(const pic_tree *t, int32_t scheme, int32_t precision, con
     return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
+pic_status pic_deposit_noalloc(const pic_tree *t, int32_t scheme, int32_t precision, const pic_particles *p,
+                               const int64_t *bin_start, const double *q, double q_uniform, double *rho,
+                               void *stream) {
+    if (!t || !valid_scheme(scheme) || !valid_precision(t, precision) || !particles_ok(t, p, precision, false))
+        return PIC_E_ARG;
+    if (!bin_start || !rho) return PIC_E_ARG;
+    if (deposit_scratch_bytes(t, scheme) > PIC_NOALLOC_SCRATCH_BYTES) return PIC_E_SCRATCH;
+    if (!t->dev) return PIC_E_STATE;
+    void *scratch = nullptr;
+    if (noalloc_scratch(&scratch) != hipSuccess) return PIC_E_HIP;
+    ProfSuspend quiet;
+    hipError_t e = precision == PIC_F64
+                       ? launch_deposit(t, scheme, p, bin_start, q, q_uniform, rho, scratch,
+                                        PIC_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream)
+                       : launch_deposit_f32(t, scheme, p, bin_start, q, q_uniform, rho, scratch,
+                                            PIC_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
+    return e == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
 pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_particles *in,
                     const int64_t *bin_start, const double *const *E, double qmdt, double dt,
                     const pic_push_params *params, int32_t n_extra, void *const *extra_in, void *const *extra_out,

@@ -92,6 +92,14 @@ class ProfScope {
     void *a_;
 };
 
+// Switches kernel timing off on this thread while it lives (for calls that
+// must create no HIP objects).
+class ProfSuspend {
+  public:
+    ProfSuspend();
+    ~ProfSuspend();
+};
+
 #define PIC_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                     \
     do {                                                                           \
         ::pic::ProfScope pic_prof_scope_(NAME, STREAM);                            \
@@ -120,6 +128,9 @@ hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
                           const int64_t *bin_start, const double *q, double q_uniform, double *rho,
                           void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t deposit_scratch_bytes(const pic_tree *t, int scheme);
+// Address of the library's device-resident deposit scratch on the current
+// device (looked up once per device; pic_kernels.hip).
+hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_status_clear(const pic_tree *t, hipStream_t s);
 hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
                        const double *const *E, double qmdt, double dt, const pic_push_params *pp, const Cols &extra,

@@ -13,6 +13,8 @@
 // stream_push  the stream benchmark of the paper's evaluation.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pic_launch.h"
 
 namespace pic {
@@ -465,6 +467,38 @@ hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *cons
 hipError_t launch_status_clear(const pic_tree *t, hipStream_t s) {
     hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(1), 0, s, t->dt.status);
     return hipGetLastError();
+}
+
+// ------------------------------------------------- deposit without allocation
+//
+// pic_deposit_noalloc keeps the deposit's per-bin partials in this
+// device-resident array instead of a caller buffer.  Each GPU the library
+// runs on holds its own copy until the process ends.  In host code the
+// array's name stands for a host-side shadow, so the device address is
+// looked up once per device (with that device current) and only that
+// address is ever handed to kernels.
+static __device__ __align__(256) unsigned char noalloc_partials[PIC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_partials));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pic

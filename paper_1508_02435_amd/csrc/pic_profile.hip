@@ -20,6 +20,7 @@ struct Rec {
     hipEvent_t a, b;
 };
 bool g_on = false;
+thread_local int g_suspended = 0;  // > 0 inside a call that must not create timing events
 std::string g_only;  // when set, only launches of this kernel name are timed
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
@@ -36,8 +37,11 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
+ProfSuspend::ProfSuspend() { ++g_suspended; }
+ProfSuspend::~ProfSuspend() { --g_suspended; }
+
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s), a_(nullptr) {
-    if (!g_on) return;
+    if (!g_on || g_suspended) return;
     if (!g_only.empty() && g_only != name) return;
     a_ = get_event();
     if (a_) hipEventRecord((hipEvent_t)a_, s);
