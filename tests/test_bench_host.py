@@ -42,3 +42,18 @@ def test_more_than_one_gpu_is_refused():
     assert res.returncode == 2
     assert "one GPU" in res.stderr
     assert res.stdout == ""
+
+
+@pytest.mark.parametrize("dim,level", [(2, 2), (2, 3), (3, 2)])
+def test_bench_poisson_solve_equals_the_oracle_support(dim, level):
+    """The benchmark's field solve (Langmuir support, outside the hot path)
+    equals the oracle's periodic Poisson solve and central-difference field,
+    which the oracle's cold-plasma and Bohm-Gross pins fix."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(dim * 10 + level)
+    n = 3 ** (dim * level)
+    rho = -(1.0 + 0.05 * rng.standard_normal(n)) / n
+    E_b = bench.poisson_field(rho, dim, level)
+    E_o = oracle.field_from_potential(oracle.poisson_periodic(rho, dim, level), dim, level)
+    assert np.abs(E_b - E_o).max() <= 1e-12 * np.abs(E_o).max()
