@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="launch-shape knob of the tree (results do not depend on it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -404,6 +406,9 @@ def main():
     _log(f"[bench] generating config {args.config}")
     wl = {2: W.config2, 3: W.config3, 4: W.config4}[args.config]()
     tree = pic.Tree(wl.tree).upload(dev)
+    for kv in args.knob:
+        name, value = kv.split("=")
+        pic.tune(name, int(value), tree)
     f32 = args.precision == "f32"
     qmdt, dt = wl.qm * wl.dt, wl.dt
     langmuir = args.config in (2, 4)
@@ -564,7 +569,8 @@ def main():
                                f", {args.scheme.upper()}, {'FP32 offsets' if f32 else 'FP64'}, {args.path} path" +
                                (", self-consistent Langmuir field (Poisson FP64 outside the timed hot path)"
                                 if langmuir else ", prescribed field"),
-                   "particles": wl.n, "leaves": int(tree.n_leaves), "scheme": args.scheme, "path": args.path},
+                   "particles": wl.n, "leaves": int(tree.n_leaves), "scheme": args.scheme, "path": args.path,
+                   "knobs": pic.tuning(tree)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in per_kernel.items()},

@@ -412,13 +412,21 @@ pic_status pic_profile_only(const char *name);
  *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's
  *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
  *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);
+ *   "step_fuse"     1 = pic_step's key pass and tile ranking run as one kernel, 0 = as
+ *                   a key pass that writes the keys and a ranking pass (default 0);
+ *   "emit_deposit"  1 = for 2D single trees whose instances are regular and a uniform
+ *                   charge, pic_step's writing pass sums each run's weights while
+ *                   the run is in LDS and the deposit only adds runs per bin; 0 = the
+ *                   deposit reads the re-binned positions again (default 0: the
+ *                   second read leaves the positions in the last-level cache for the
+ *                   next step's key pass, which makes up for it);
  *   "regular_tables" (process default only) 1 = trees created afterwards get Peano
  *                   rank tables for their regular instances (up to 2^21 cells per
  *                   level), which the arithmetic kernels and the FP32 form use;
  *                   0 = none, every tree takes the descent kernels (default 1).
  * Every setting gives the same bins, order and particle state; "deposit_lanes"
- * changes the order of the deposit's sums, so the charge differs in rounding
- * only (far inside the stated tolerance).  pic_scratch_bytes covers all settings.
+ * and "emit_deposit" change the order of the deposit's sums, so the charge
+ * differs in rounding only (far inside the stated tolerance).  pic_scratch_bytes covers all settings.
  * Affects calls enqueued afterwards.  Unknown names or values: PIC_E_ARG
  * (pic_tune_get returns -1).
  */

@@ -20,7 +20,8 @@ from . import Stepper32, tune, tuning
 
 # knobs each path depends on
 SPACES = {
-    "fused_f64": {"step_tile": (2048, 1024), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16)},
+    "fused_f64": {"step_tile": (2048, 1024), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16),
+                  "emit_deposit": (0, 1)},
     "calls_f64": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1), "deposit_lanes": (64, 32, 16)},
     "f32": {"xcd_tiles": (1, 0)},

@@ -278,6 +278,12 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
     } else if (k == "emit_threads") {
         if (!one_of({512, 1024})) return false;
         g.emit_threads = (int)value;
+    } else if (k == "step_fuse") {
+        if (!one_of({0, 1})) return false;
+        g.step_fuse = (int)value;
+    } else if (k == "emit_deposit") {
+        if (!one_of({0, 1})) return false;
+        g.emit_deposit = (int)value;
     } else {
         return false;
     }
@@ -297,6 +303,8 @@ int64_t tune_get(const Tuning &g, const char *name) {
     if (k == "regular_tables") return g.regular_tables;
     if (k == "xcd_tiles") return g.xcd_tiles;
     if (k == "emit_threads") return g.emit_threads;
+    if (k == "step_fuse") return g.step_fuse;
+    if (k == "emit_deposit") return g.emit_deposit;
     if (k == "deposit_bpw") return g.deposit_bpw;
     return -1;
 }

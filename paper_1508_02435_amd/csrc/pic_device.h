@@ -362,6 +362,60 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
     return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
 }
 
+// Key of one particle of the fused step: pushes it (push_one, so the same
+// state and bin as every other pass) and returns 2 * new bin + arrived.  A
+// particle stays iff its slot lies in its new bin's old segment.  When the
+// slot lies in the old segment of the bin of its old cell, that is the case
+// iff the two bins agree; the lanes of a wavefront mostly share that cell, so
+// its bin and segment come from scalar loads.  Other lanes load the new bin's
+// segment.  Call with every lane of the wavefront that holds a particle.
+// xv, vv: the particle's state, loaded by the caller (and pushed here).
+template <int D, int SCHEME, bool REG, bool MULTI>
+__device__ __forceinline__ uint32_t step_key_one(const DevTree &t, const DevInst &in0, const F64Ptrs &P, int64_t p,
+                                                 double (&xv)[D], double (&vv)[D], double qmdt0, double dt0,
+                                                 const double *qa, const double *da, const int64_t *inst_start,
+                                                 const int64_t *old_start, uint32_t n_bins, const int32_t *lds,
+                                                 int lds_n, uint32_t &bad) {
+    int ii = 0;
+    if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+    const DevInst &in = MULTI ? t.inst[ii] : in0;
+    const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
+    const double dt = (MULTI && da) ? da[ii] : dt0;
+    // finest cell of the old position (PIT on a regular instance: its bin)
+    uint32_t cold = 0;
+    if (SCHEME == PIC_PIT && REG) {
+        uint32_t m = 1;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double y = x_scaled(xv[k], in.Sd);
+            cold += __umul24(min((uint32_t)max(y, 0.0), (uint32_t)in.S - 1u), m);
+            m = __umul24(m, (uint32_t)in.S);
+        }
+    }
+    uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
+    if (b >= n_bins) bad |= PIC_DEV_RANGE;
+    b = min(b, n_bins - 1);
+    bool stay = false, known = !old_start;
+    if (SCHEME == PIC_PIT && REG && !MULTI && old_start) {
+        uint64_t pend = __ballot(1);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            if (!pend) break;
+            const uint32_t cu = (uint32_t)__builtin_amdgcn_readlane((int)cold, __builtin_ctzll(pend));
+            const bool mine = cold == cu;
+            pend &= ~__ballot(mine);
+            const uint32_t ob = (uint32_t)in.leaf_off + ld_const(t.peano_tab, (uint32_t)in.ptab + cu);
+            const int64_t s0 = ld_const(old_start, ob), s1 = ld_const(old_start, ob + 1u);
+            if (mine && s0 <= p && p < s1) {
+                stay = b == ob;
+                known = true;
+            }
+        }
+    }
+    if (!known) stay = old_start[b] <= p && p < old_start[b + 1];
+    return 2u * b + (stay ? 0u : 1u);
+}
+
 // Exclusive scan of one uint32 per thread over a 256-thread block; returns the
 // exclusive prefix and writes the block total to *total.  `wsum` is 4 words of
 // LDS.  Fixed combination order, so the result is deterministic.
@@ -416,6 +470,9 @@ struct RebinScratch {
     uint32_t *khead;      // 2*n_bins (zeroed per call): runs of a key past KLIST_CAP, a linked list
     uint32_t *knext;      // n_tiles * TILE: next run of that list (run address + 1; 0 ends it)
     uint32_t *wave_bin;   // n_tiles * TILE / 64: old bin of slot 64 c (sorted input), for the FP32 form
+    uint32_t *run_pos;    // n_tiles * TILE: fused step, a run's position among all runs sorted by (key, tile)
+    double *run_part;     // fused step with the deposit in the writing pass: per run (by run_pos) its
+                          // particles' summed weights, ns doubles
 };
 
 // Scan shapes: the three-call re-bin scans SCAN_TILE keys per block, the
@@ -424,7 +481,7 @@ constexpr int SCAN_IPT = 8;
 constexpr int SCAN_TILE = 256 * SCAN_IPT;
 constexpr uint64_t ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_VAL = (1ull << 62) - 1;
 constexpr int SP_THREADS = 256;
-constexpr int SP_KPT = 16;                      // keys per thread
+constexpr int SP_KPT = 4;                       // keys per thread
 constexpr int SP_KEYS = SP_THREADS * SP_KPT;
 
 // Pass 3b: a run's place among the runs of its key is the particle count of
@@ -435,7 +492,7 @@ constexpr int SP_KEYS = SP_THREADS * SP_KPT;
 // bitonic sort, beyond that by counting the smaller addresses per run.
 template <int W>
 __device__ __forceinline__ void place_sorted(const RebinScratch &sc, const uint32_t *lst, uint32_t l0, uint32_t len,
-                                             uint32_t kb, int sub) {
+                                             uint32_t kb, int sub, uint32_t *pos = nullptr, uint32_t pos0 = 0u) {
     uint32_t a = 0xffffffffu, c = 0;
     if ((uint32_t)sub < len) {
         a = lst[l0 + sub];
@@ -459,7 +516,10 @@ __device__ __forceinline__ void place_sorted(const RebinScratch &sc, const uint3
         const uint32_t y = (uint32_t)__shfl_up((int)x, o, W);
         if (sub >= o) x += y;
     }
-    if ((uint32_t)sub < len) sc.run_dest[a] = kb + x - c;
+    if ((uint32_t)sub < len) {
+        sc.run_dest[a] = kb + x - c;
+        if (pos) pos[a] = pos0 + (uint32_t)sub;   // the run's place among the key's runs
+    }
 }
 
 // Entries at the head of a tile's run table that the emit pass loads with
@@ -503,6 +563,66 @@ __device__ __forceinline__ void group_sum(double (&acc)[N]) {
         if (G >= 16) acc[c] = __dadd_rn(acc[c], dpp_f64<0x140>(acc[c]));  // row_mirror
         if (G >= 32) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], 16, 64));
         if (G >= 64) acc[c] = __dadd_rn(acc[c], __shfl_xor(acc[c], 32, 64));
+    }
+}
+
+// Accumulate one particle's restriction weights: PIT per leaf corner, PIDT
+// per stencil slot of the owning vertex.
+template <int D, int SCHEME, bool REG, int NS>
+__device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp, int e, double s, uint32_t su,
+                                            double rinv, double qp, bool use_q, double (&acc)[NS]) {
+    uint32_t bad = 0;
+    Axis ax[D];
+    uint32_t a[D];
+    double f[D], g[D];
+    if (REG && SCHEME == PIC_PIT) {
+        // the stored positions lie in [0,1), so the cell is floor(y) and
+        // f = y - floor(y) is y - I exactly, without the integer cell
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double y = __dmul_rn(xp[k], in.Sd);
+            f[k] = __dsub_rn(y, floor(y));
+            g[k] = __dsub_rn(1.0, f[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
+            const uint32_t I = ax[k].T >> 1;
+            a[k] = REG ? I : div_pow3(I, e);
+            f[k] = REG ? __dsub_rn(ax[k].y, (double)I) : __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
+            g[k] = __dsub_rn(1.0, f[k]);
+        }
+    }
+    if (SCHEME == PIC_PIT) {
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) {
+            double wc = (c & 1) ? f[0] : g[0];
+#pragma unroll
+            for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
+            acc[c] = __dadd_rn(acc[c], use_q ? __dmul_rn(qp, wc) : wc);
+        }
+    } else {
+        // The owner is the corner nearest to the particle.  Per axis the
+        // particle's two corner weights (g, f) land on stencil offsets {0,+1}
+        // (owner below) or {-1,0} (owner above); the 3^d slot weights are the
+        // tensor product of these per-axis triples, so every slot is updated
+        // branch-free (absent ones with +0).
+        double u[D][3];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const bool up = ax[k].T >= (2u * a[k] + 1u) * su;
+            u[k][0] = up ? g[k] : 0.0;
+            u[k][1] = up ? f[k] : g[k];
+            u[k][2] = up ? 0.0 : f[k];
+        }
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            double wc = u[0][sl % 3];
+            wc = __dmul_rn(wc, u[1][(sl / 3) % 3]);
+            if (D == 3) wc = __dmul_rn(wc, u[D - 1][sl / 9]);
+            acc[sl] = __dadd_rn(acc[sl], use_q ? __dmul_rn(qp, wc) : wc);
+        }
     }
 }
 

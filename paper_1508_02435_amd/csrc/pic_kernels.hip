@@ -70,66 +70,6 @@ __global__ __launch_bounds__(256) void k_locate(DevTree t, DevInst in0, F64Ptrs 
 
 // ------------------------------------------------------------- block scans
 
-// Accumulate one particle's restriction weights: PIT per leaf corner, PIDT
-// per stencil slot of the owning vertex.
-template <int D, int SCHEME, bool REG, int NS>
-__device__ __forceinline__ void deposit_one(const DevInst &in, const double *xp, int e, double s, uint32_t su,
-                                            double rinv, double qp, bool use_q, double (&acc)[NS]) {
-    uint32_t bad = 0;
-    Axis ax[D];
-    uint32_t a[D];
-    double f[D], g[D];
-    if (REG && SCHEME == PIC_PIT) {
-        // the stored positions lie in [0,1), so the cell is floor(y) and
-        // f = y - floor(y) is y - I exactly, without the integer cell
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double y = __dmul_rn(xp[k], in.Sd);
-            f[k] = __dsub_rn(y, floor(y));
-            g[k] = __dsub_rn(1.0, f[k]);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            ax[k] = scale_axis(xp[k], in.Sd, in.S, bad);
-            const uint32_t I = ax[k].T >> 1;
-            a[k] = REG ? I : div_pow3(I, e);
-            f[k] = REG ? __dsub_rn(ax[k].y, (double)I) : __dmul_rn(__dsub_rn(ax[k].y, (double)a[k] * s), rinv);
-            g[k] = __dsub_rn(1.0, f[k]);
-        }
-    }
-    if (SCHEME == PIC_PIT) {
-#pragma unroll
-        for (int c = 0; c < (1 << D); ++c) {
-            double wc = (c & 1) ? f[0] : g[0];
-#pragma unroll
-            for (int k = 1; k < D; ++k) wc = __dmul_rn(wc, ((c >> k) & 1) ? f[k] : g[k]);
-            acc[c] = __dadd_rn(acc[c], use_q ? __dmul_rn(qp, wc) : wc);
-        }
-    } else {
-        // The owner is the corner nearest to the particle.  Per axis the
-        // particle's two corner weights (g, f) land on stencil offsets {0,+1}
-        // (owner below) or {-1,0} (owner above); the 3^d slot weights are the
-        // tensor product of these per-axis triples, so every slot is updated
-        // branch-free (absent ones with +0).
-        double u[D][3];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const bool up = ax[k].T >= (2u * a[k] + 1u) * su;
-            u[k][0] = up ? g[k] : 0.0;
-            u[k][1] = up ? f[k] : g[k];
-            u[k][2] = up ? 0.0 : f[k];
-        }
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) {
-            double wc = u[0][sl % 3];
-            wc = __dmul_rn(wc, u[1][(sl / 3) % 3]);
-            if (D == 3) wc = __dmul_rn(wc, u[D - 1][sl / 9]);
-            acc[sl] = __dadd_rn(acc[sl], use_q ? __dmul_rn(qp, wc) : wc);
-        }
-    }
-}
-
 // G lanes per bin (64/G bins per wavefront).  A bin's particles are taken in
 // batches of G*K; all loads of a batch are issued before the first is used,
 // so a bin of up to G*K particles costs one memory latency after its offsets

@@ -35,10 +35,13 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct RebinLayout {
     size_t tile_bin, perm, run_key, run_info, run_dest, tile_nruns, key_cnt, key_nruns, key_fill, key_cn, key_base,
         list_off,
-        list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, wave_bin, total;
+        list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, wave_bin, run_pos, run_part, bin_part,
+        total;
 };
 
-inline RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
+// run_ns: doubles of each run's deposit partial when the writing pass of the
+// fused step deposits (0 otherwise).
+inline RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile, int run_ns = 0) {
     RebinLayout L{};
     const int64_t tiles = (n + tile - 1) / tile;
     const int64_t slots = tiles * tile;
@@ -67,6 +70,9 @@ inline RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile) {
     L.klist = o; o = align256(o + keys * KLIST_CAP * 4);
     L.knext = o; o = align256(o + slots * 4);
     L.wave_bin = o; o = align256(o + (slots / 64 + 1) * 4);
+    L.run_pos = o; o = align256(o + slots * 4);
+    L.run_part = o; o = align256(o + slots * 8 * run_ns);
+    L.bin_part = o; o = align256(o + n_bins * 8 * run_ns);
     L.total = o;
     return L;
 }
@@ -95,6 +101,8 @@ inline RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.khead = (uint32_t *)(base + L.khead);
     sc.knext = (uint32_t *)(base + L.knext);
     sc.wave_bin = (uint32_t *)(base + L.wave_bin);
+    sc.run_pos = (uint32_t *)(base + L.run_pos);
+    sc.run_part = (double *)(base + L.run_part);
     return sc;
 }
 
@@ -103,6 +111,11 @@ inline RebinScratch bind_scratch(const RebinLayout &L, char *base) {
 // every 64th slot (pic_rebin.hip).
 void launch_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_start, int64_t n_bins, int64_t n, int tile,
                  const RebinScratch &sc, hipStream_t s);
+// The fused step's key pass and tile ranking in one kernel (pic_rank.hip);
+// keys_out (nullable) receives every particle's key as well.
+void launch_keyrank(const pic_tree *t, int scheme, const F64Ptrs &P, int64_t n, double qmdt, double dt,
+                    const double *qa, const double *da, const int64_t *inst_start, const int64_t *old_start,
+                    uint32_t n_bins, int tile, const RebinScratch &sc, uint32_t *keys_out, hipStream_t s);
 // The tile ranking of the fused step over keys in memory (pic_rank.hip).
 void launch_group(const uint32_t *keys, int64_t n, int tile, const RebinScratch &sc, hipStream_t s);
 // Per-vertex sums of the deposit's per-bin partials (pic_kernels.hip); `reg`

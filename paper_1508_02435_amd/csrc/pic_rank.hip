@@ -102,47 +102,16 @@ __device__ __forceinline__ void rank_clear(RankSmem<IPT> &S) {
     S.msk[tid >> 6][tid & 63] = 0ull;
 }
 
-// Ranks the tile's keys (slot w*64*IPT + j*64 + lane of thread (w, lane),
-// ~0 past the end): writes the tile's runs (key, tile-local start | count <<
-// 16), adds the per-key counts, and stores run index | rank << 16 for every
-// particle.  The table must be cleared and all threads past a barrier.
-template <int IPT>
-__device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key)[IPT], int64_t tile, int64_t lo,
-                                          const RebinScratch &sc, uint32_t *meta) {
-    using RS = RankShape<IPT>;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t slot[IPT], rk[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        slot[j] = 0u;
-        if (key[j] != ~0u) {
-            slot[j] = table_find<RS::HB>(S.key, key[j]);
-            if (slot[j] == ~0u) slot[j] = table_insert<RS::HB>(S.key, key[j]);
-        }
-    }
-    // wavefront-scope atomic loads and stores: plain LDS accesses that the
-    // compiler may neither forward nor reorder against the other lanes' ones
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        rk[j] = 0u;
-        if (key[j] == ~0u) continue;
-        uint8_t *tg = &S.tag[w][slot[j]];
-        uint16_t *cw = &S.wc[w][slot[j]];
-        __hip_atomic_store(tg, (uint8_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint32_t rep = __hip_atomic_load(tg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        unsigned long long *mk = &S.msk[w][rep];
-        __hip_atomic_fetch_or(mk, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint64_t m = __hip_atomic_load(mk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint32_t base = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint32_t below = lanes_below(m);
-        if (below == 0u) {
-            __hip_atomic_store(cw, (uint16_t)(base + (uint32_t)__popcll(m)), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WAVEFRONT);
-            __hip_atomic_store(mk, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        }
-        rk[j] = base + below;
-    }
-    __syncthreads();
+// Compaction of a ranked tile (the key table holds key + 1 per occupied
+// slot, wc[w][slot] the count of wavefront w): in slot order (a block scan)
+// every occupied slot gets its run index and tile-local start, written to the
+// run table with the key; each run adds (count, 1) to its key's counter and
+// lists its address; the per-wavefront counts become per-wavefront offsets
+// (counts of the earlier wavefronts) and the key table maps slot -> run
+// index.  Called by all threads after a barrier; ends with a barrier.
+template <int IPT, typename SM>
+__device__ __forceinline__ void tile_compact(SM &S, int64_t tile, int64_t lo, const RebinScratch &sc) {
+    const int tid = threadIdx.x;
     // compaction in slot order (a block scan): run index and tile-local
     // start of every occupied slot; the per-wave counts become per-wave
     // offsets (counts of the earlier wavefronts)
@@ -197,11 +166,173 @@ __device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key
     }
     __syncthreads();
     if (tid == 0) sc.tile_nruns[tile] = total & 0xffffu;
+}
+
+// Ranks the tile's keys (slot w*64*IPT + j*64 + lane of thread (w, lane),
+// ~0 past the end): writes the tile's runs (key, tile-local start | count <<
+// 16), adds the per-key counts, and stores run index | rank << 16 for every
+// particle.  The table must be cleared and all threads past a barrier.
+template <int IPT>
+__device__ __forceinline__ void tile_rank(RankSmem<IPT> &S, const uint32_t (&key)[IPT], int64_t tile, int64_t lo,
+                                          const RebinScratch &sc, uint32_t *meta) {
+    using RS = RankShape<IPT>;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t slot[IPT], rk[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        slot[j] = 0u;
+        if (key[j] != ~0u) {
+            slot[j] = table_find<RS::HB>(S.key, key[j]);
+            if (slot[j] == ~0u) slot[j] = table_insert<RS::HB>(S.key, key[j]);
+        }
+    }
+    // wavefront-scope atomic loads and stores: plain LDS accesses that the
+    // compiler may neither forward nor reorder against the other lanes' ones
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        rk[j] = 0u;
+        if (key[j] == ~0u) continue;
+        uint8_t *tg = &S.tag[w][slot[j]];
+        uint16_t *cw = &S.wc[w][slot[j]];
+        __hip_atomic_store(tg, (uint8_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t rep = __hip_atomic_load(tg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        unsigned long long *mk = &S.msk[w][rep];
+        __hip_atomic_fetch_or(mk, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint64_t m = __hip_atomic_load(mk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t base = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t below = lanes_below(m);
+        if (below == 0u) {
+            __hip_atomic_store(cw, (uint16_t)(base + (uint32_t)__popcll(m)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_store(mk, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        rk[j] = base + below;
+    }
+    __syncthreads();
+    tile_compact<IPT>(S, tile, lo, sc);
     const int64_t pbase = lo + (int64_t)w * 64 * IPT + lane;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         if (key[j] == ~0u) continue;
         meta[pbase + 64 * j] = S.key[slot[j]] | ((S.wc[w][slot[j]] + rk[j]) << 16);
+    }
+}
+
+// ------------------------------------------- fused key + ranking, by match
+//
+// The key pass and the tile ranking in one kernel: a tile of 256 * IPT
+// particles per block, wavefront w pushing the slots w*64*IPT + j*64 + lane
+// in rounds j (push_one, so the same state and bin as every other pass).
+// Inside a round the lanes with equal keys are found by matching: the
+// wavefront takes the key of its first unmatched lane, ballots the lanes
+// holding it, and repeats until every lane is matched (as many rounds as
+// the 64 particles have distinct keys, which sorted input keeps small).
+// Only one lane per distinct key (the lowest) touches LDS: it finds or
+// inserts the key in the tile's table and advances its wavefront's count of
+// it; the others take the table slot and the count from it by a lane
+// shuffle, and their rank among the lanes below them from the match mask.
+// The ranks follow slot order and do not depend on timing.
+
+template <int IPT>
+struct alignas(16) MatchSmem {
+    uint32_t key[RankShape<IPT>::H];            // key + 1 (0: empty); run index after compaction
+    uint16_t wc[4][RankShape<IPT>::H];          // per wavefront count of each slot, then its offset
+    uint32_t wsum[4];
+};
+
+template <int IPT>
+__device__ __forceinline__ void match_clear(MatchSmem<IPT> &S) {
+    static_assert(offsetof(MatchSmem<IPT>, wc) == sizeof(S.key), "layout");
+    constexpr int N16 = (int)(sizeof(S.key) + sizeof(S.wc)) / 16;
+    uint4 *p = (uint4 *)&S.key[0];
+    for (int i = threadIdx.x; i < N16; i += RB_THREADS) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Rank of this lane's key (~0: no particle) among the wavefront's earlier
+// particles with the same key; returns table slot | rank << 16.
+template <int IPT>
+__device__ __forceinline__ uint32_t match_rank(MatchSmem<IPT> &S, uint32_t key, int w) {
+    using RS = RankShape<IPT>;
+    const bool live = key != ~0u;
+    uint64_t pend = __ballot(live), mine = 0;
+    while (pend) {
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, __builtin_ctzll(pend));
+        const uint64_t m = __ballot(key == k);
+        pend &= ~m;
+        if (key == k) mine = m;
+    }
+    const uint32_t below = lanes_below(mine);
+    uint32_t hs = 0u, base = 0u;
+    if (live && below == 0u) {
+        hs = table_find<RS::HB>(S.key, key);
+        if (hs == ~0u) hs = table_insert<RS::HB>(S.key, key);
+        base = S.wc[w][hs];
+        S.wc[w][hs] = (uint16_t)(base + (uint32_t)__popcll(mine));
+    }
+    const int leader = live ? __builtin_ctzll(mine) : (int)__lane_id();
+    hs = (uint32_t)__shfl((int)hs, leader, 64);
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    return live ? (hs | ((base + below) << 16)) : ~0u;
+}
+
+template <int D, int SCHEME, bool REG, bool MULTI, int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_keyrank(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                            double qmdt0, double dt0, const double *qa,
+                                                            const double *da, const int64_t *inst_start,
+                                                            const int64_t *old_start, uint32_t n_bins,
+                                                            RebinScratch sc, uint32_t *keys_out) {
+    using RS = RankShape<IPT>;
+    __shared__ MatchSmem<IPT> S;
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t lo = tile * RS::TILE;
+    match_clear<IPT>(S);
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    __syncthreads();   // table cleared
+    const int64_t pbase = lo + (int64_t)w * 64 * IPT + lane;
+    uint32_t bad = 0;
+    // the next round's state is loaded while this round is pushed and ranked
+    double xn[D], vn[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xn[k] = pbase < n ? P.x[k][pbase] : 0.0;
+        vn[k] = pbase < n ? P.v[k][pbase] : 0.0;
+    }
+    uint32_t res[IPT];   // per particle: table slot | rank << 16
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t p = pbase + 64 * j;
+        double xv[D], vv[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xv[k] = xn[k];
+            vv[k] = vn[k];
+        }
+        if (j + 1 < IPT && p + 64 < n) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                xn[k] = P.x[k][p + 64];
+                vn[k] = P.v[k][p + 64];
+            }
+        }
+        uint32_t key = ~0u;
+        if (p < n) {
+            key = step_key_one<D, SCHEME, REG, MULTI>(t, in0, P, p, xv, vv, qmdt0, dt0, qa, da, inst_start,
+                                                      old_start, n_bins, lds, lds_n, bad);
+            if (keys_out) keys_out[p] = key;
+        }
+        res[j] = match_rank<IPT>(S, key, w);
+    }
+    if (bad) flag_status(t.status, bad);
+    __syncthreads();
+    tile_compact<IPT>(S, tile, lo, sc);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t r = res[j];
+        if (r == ~0u) continue;
+        const uint32_t hs = r & 0xffffu;
+        sc.meta[pbase + 64 * j] = S.key[hs] | (((uint32_t)S.wc[w][hs] + (r >> 16)) << 16);
     }
 }
 
@@ -350,7 +481,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_step_scan(uint32_t n_keys, uint3
 // destination is the key base plus the counts of the runs with smaller
 // addresses, found by comparing against every run of the key in turn.
 __device__ __forceinline__ void place_counted(const RebinScratch &sc, const uint32_t *lst, uint32_t l0, uint32_t len,
-                                              uint32_t kb, int lane) {
+                                              uint32_t kb, int lane, uint32_t pos0) {
     uint32_t a0 = ~0u, c0 = 0u, a1 = ~0u, c1 = 0u;
     if ((uint32_t)lane < len) {
         a0 = lst[l0 + lane];
@@ -360,7 +491,7 @@ __device__ __forceinline__ void place_counted(const RebinScratch &sc, const uint
         a1 = lst[l0 + 64 + lane];
         c1 = sc.run_info[a1] >> 16;
     }
-    uint32_t b0 = 0u, b1 = 0u;
+    uint32_t b0 = 0u, b1 = 0u, r0 = 0u, r1 = 0u;
     for (int j = 0; j < 64; ++j) {
         const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)a0, j);
         const uint32_t y0 = (uint32_t)__builtin_amdgcn_readlane((int)c0, j);
@@ -368,42 +499,55 @@ __device__ __forceinline__ void place_counted(const RebinScratch &sc, const uint
         const uint32_t y1 = (uint32_t)__builtin_amdgcn_readlane((int)c1, j);
         b0 += (x0 < a0 ? y0 : 0u) + (x1 < a0 ? y1 : 0u);
         b1 += (x0 < a1 ? y0 : 0u) + (x1 < a1 ? y1 : 0u);
+        r0 += (x0 < a0 ? 1u : 0u) + (x1 < a0 ? 1u : 0u);
+        r1 += (x0 < a1 ? 1u : 0u) + (x1 < a1 ? 1u : 0u);
     }
-    if ((uint32_t)lane < len) sc.run_dest[a0] = kb + b0;
-    if ((uint32_t)lane + 64u < len) sc.run_dest[a1] = kb + b1;
+    if ((uint32_t)lane < len) {
+        sc.run_dest[a0] = kb + b0;
+        sc.run_pos[a0] = pos0 + r0;
+    }
+    if ((uint32_t)lane + 64u < len) {
+        sc.run_dest[a1] = kb + b1;
+        sc.run_pos[a1] = pos0 + r1;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_keys) {
+    // Besides its destination every run gets its position among all runs
+    // sorted by (key, tile): the key's list offset plus its rank among the
+    // key's runs by address (tile order).
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4, sub = lane & 15;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t k0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4; k0 < n_keys;
          k0 += waves * 4) {
         const int64_t key = k0 + grp;
-        uint32_t len = 0, kb = 0;
+        uint32_t len = 0, kb = 0, lo = 0;
         if (key < n_keys) {
             len = (uint32_t)sc.key_cn[key];
             kb = sc.key_base[key];
+            lo = sc.list_off[key];
         }
         if (__ballot(len != 0u) == 0) continue;   // four empty keys
-        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * KLIST_CAP), len, kb, sub);
+        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * KLIST_CAP), len, kb, sub, sc.run_pos, lo);
         for (int g = 0; g < 4; ++g) {
             const int64_t gk = k0 + g;
             const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
             const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
+            const uint32_t glo = (uint32_t)__shfl((int)lo, g * 16, 64);
             if (glen <= 16) continue;
             if (glen <= 64u) {
-                place_sorted<64>(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane);
+                place_sorted<64>(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane, sc.run_pos, glo);
                 continue;
             }
             if (glen <= (uint32_t)KLIST_CAP) {
-                place_counted(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane);
+                place_counted(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane, glo);
                 continue;
             }
             // a long list: gathered into its exact slot range of the list
             // array (direct part by the lanes, linked part by lane 0), then
             // every run counts the runs before it
-            const uint32_t l0 = sc.list_off[gk];
+            const uint32_t l0 = glo;
             for (int i = lane; i < KLIST_CAP; i += 64) sc.list[l0 + i] = sc.klist[gk * KLIST_CAP + i];
             if (lane == 0) {
                 uint32_t q = KLIST_CAP;
@@ -412,18 +556,50 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
             __threadfence();   // lane 0's entries visible to the other lanes' loads
             for (uint32_t q = lane; q < glen; q += 64) {
                 const uint32_t a = sc.list[l0 + q];
-                uint32_t before = 0;
+                uint32_t before = 0, rank = 0;
                 for (uint32_t j = l0; j < l0 + glen; ++j) {
                     const uint32_t bb = sc.list[j];
-                    if (bb < a) before += sc.run_info[bb] >> 16;
+                    if (bb < a) {
+                        before += sc.run_info[bb] >> 16;
+                        ++rank;
+                    }
                 }
                 sc.run_dest[a] = gkb + before;
+                sc.run_pos[a] = l0 + rank;
             }
         }
     }
 }
 
 // ----------------------------------------------------------------- launchers
+
+void launch_keyrank(const pic_tree *t, int scheme, const F64Ptrs &P, int64_t n, double qmdt, double dt,
+                    const double *qa, const double *da, const int64_t *inst_start, const int64_t *old_start,
+                    uint32_t n_bins, int tile, const RebinScratch &sc, uint32_t *keys_out, hipStream_t s) {
+    if (n == 0) return;
+    const dim3 g((unsigned)((n + tile - 1) / tile)), b(RB_THREADS);
+#define PIC_KR(D, SCH, REG, MULTI, IPT)                                                                      \
+    PIC_LAUNCH("step_keyrank", (k_step_keyrank<D, SCH, REG, MULTI, IPT>), g, b, 0, s, t->dt, t->inst0, P, n, qmdt, \
+               dt, qa, da, inst_start, old_start, n_bins, sc, keys_out)
+#define PIC_KR_T(D, SCH, REG, MULTI)                                                                         \
+    do {                                                                                                     \
+        if (tile == 1024) PIC_KR(D, SCH, REG, MULTI, 4); else PIC_KR(D, SCH, REG, MULTI, 8);                \
+    } while (0)
+#define PIC_KR_RM(D, SCH)                                                                                    \
+    do {                                                                                                     \
+        const bool multi = t->n_inst > 1, reg = t->reg_kernels != 0;                                         \
+        if (multi) { if (reg) PIC_KR_T(D, SCH, true, true); else PIC_KR_T(D, SCH, false, true); }            \
+        else { if (reg) PIC_KR_T(D, SCH, true, false); else PIC_KR_T(D, SCH, false, false); }                \
+    } while (0)
+    if (t->dim == 2) {
+        if (scheme == PIC_PIT) PIC_KR_RM(2, 0); else PIC_KR_RM(2, 1);
+    } else {
+        if (scheme == PIC_PIT) PIC_KR_RM(3, 0); else PIC_KR_RM(3, 1);
+    }
+#undef PIC_KR_RM
+#undef PIC_KR_T
+#undef PIC_KR
+}
 
 void launch_group(const uint32_t *keys, int64_t n, int tile, const RebinScratch &sc, hipStream_t s) {
     const int64_t tiles = (n + tile - 1) / tile;

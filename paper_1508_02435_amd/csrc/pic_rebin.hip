@@ -552,7 +552,10 @@ __global__ void k_rebin_prep(uint32_t *zero, int64_t n_zero, const int64_t *old_
 size_t rebin_scratch_bytes(const pic_tree *t, int64_t n, int scheme) {
     // large enough for every supported tile size
     const int64_t nb = n_bins_of(t, scheme);
-    return std::max({rebin_layout(n, nb, 1024).total, rebin_layout(n, nb, 2048).total, rebin_layout(n, nb, 4096).total});
+    // the 2D fused step deposits in its writing pass: one partial per run
+    const int ns = t->dim == 2 ? (scheme == PIC_PIT ? 4 : 9) : 0;
+    return std::max({rebin_layout(n, nb, 1024, ns).total, rebin_layout(n, nb, 2048, ns).total,
+                     rebin_layout(n, nb, 4096).total});
 }
 
 template <int IPT>

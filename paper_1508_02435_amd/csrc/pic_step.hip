@@ -11,8 +11,9 @@
 
 namespace pic {
 
-// Key pass: one particle per thread, pushed, its key
-// 2*bin + arrived written out (the state itself is not).
+// Key pass of the unfused form: one particle per thread, pushed, its key
+// 2*bin + arrived written out (the state itself is not); it also clears the
+// per-call counters.
 template <int D, int SCHEME, bool REG, bool MULTI>
 __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
@@ -24,11 +25,6 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += stride) zero[i] = 0u;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        int ii = 0;
-        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
-        const DevInst &in = MULTI ? t.inst[ii] : in0;
-        const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
-        const double dt = (MULTI && da) ? da[ii] : dt0;
         uint32_t bad = 0;
         double xv[D], vv[D];
 #pragma unroll
@@ -36,74 +32,211 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
             xv[k] = P.x[k][p];
             vv[k] = P.v[k][p];
         }
-        // finest cell of the old position (PIT on a regular instance: its bin)
-        uint32_t cold = 0;
-        if (SCHEME == PIC_PIT && REG) {
-            uint32_t m = 1;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double y = x_scaled(xv[k], in.Sd);
-                cold += __umul24(min((uint32_t)max(y, 0.0), (uint32_t)in.S - 1u), m);
-                m = __umul24(m, (uint32_t)in.S);
-            }
-        }
-        uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
-        if (b >= n_bins) bad |= PIC_DEV_RANGE;
-        b = min(b, n_bins - 1);
-        // A particle stays iff its slot lies in its new bin's old segment.
-        // When the slot lies in the old segment of the bin of its old cell,
-        // that is the case iff the two bins agree; the lanes of a wavefront
-        // mostly share that cell, so its bin and segment come from scalar
-        // loads.  Other lanes load the new bin's segment.
-        bool stay = false, known = !old_start;
-        if (SCHEME == PIC_PIT && REG && !MULTI && old_start) {
-            uint64_t pend = __ballot(1);
-#pragma unroll
-            for (int it = 0; it < 2; ++it) {
-                if (!pend) break;
-                const uint32_t cu = (uint32_t)__builtin_amdgcn_readlane((int)cold, __builtin_ctzll(pend));
-                const bool mine = cold == cu;
-                pend &= ~__ballot(mine);
-                const uint32_t ob = (uint32_t)in.leaf_off + ld_const(t.peano_tab, (uint32_t)in.ptab + cu);
-                const int64_t s0 = ld_const(old_start, ob), s1 = ld_const(old_start, ob + 1u);
-                if (mine && s0 <= p && p < s1) {
-                    stay = b == ob;
-                    known = true;
-                }
-            }
-        }
-        if (!known) stay = old_start[b] <= p && p < old_start[b + 1];
-        key_out[p] = 2u * b + (stay ? 0u : 1u);
+        key_out[p] = step_key_one<D, SCHEME, REG, MULTI>(t, in0, P, p, xv, vv, qmdt0, dt0, qa, da, inst_start,
+                                                         old_start, n_bins, lds, lds_n, bad);
         if (bad) flag_status(t.status, bad);
     }
 }
 
+// ------------------------------------------------- deposit in the writing pass
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Tile-local sorted start and sorted-list position of run rid of the tile at
+// lo.  Read at run ends only (a few per wavefront), from the run tables.
+__device__ __forceinline__ uint32_t run_start_of(const uint32_t *run_info, int64_t lo, uint32_t rid) {
+    return run_info[lo + rid] & 0xffffu;
+}
+__device__ __forceinline__ uint32_t run_place_of(const uint32_t *run_pos, int64_t lo, uint32_t rid) {
+    return run_pos[lo + rid];
+}
+
+constexpr uint32_t EDGE_NONE = 0xffffu, EDGE_VALID = 1u << 16, EDGE_CONT = 1u << 17;
+
+// A run ending in wavefront w (first sorted slot wq0): its sum is complete
+// when the run started in w; otherwise it is w's first piece of the run.
+template <int NSD>
+__device__ __forceinline__ void emit_finish(uint32_t r, const double (&v)[NSD], uint32_t wq0, int w,
+                                            double (*s_edge)[2][NSD], uint32_t (*s_erid)[2], int64_t lo,
+                                            const uint32_t *run_info, const uint32_t *run_pos, double *run_part) {
+    if (run_start_of(run_info, lo, r) >= wq0) {
+        double *o = run_part + (int64_t)run_place_of(run_pos, lo, r) * NSD;
+#pragma unroll
+        for (int c = 0; c < NSD; ++c) o[c] = v[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NSD; ++c) s_edge[w][0][c] = v[c];
+        s_erid[w][0] = r | EDGE_VALID;
+    }
+}
+
+// One wavefront's share of the writing pass's deposit: its sorted slots
+// [64 IPT w, 64 IPT (w+1)) in rounds of 64 (positions staged in s_val[0..D)).
+// One step of a segmented inclusive scan over a wavefront: each lane of the
+// rows in ROWS takes the partial sums of the lane that the DPP pattern CTRL
+// names when both carry the same run id.  Runs are contiguous, so equal ids
+// at both ends of a step mean one run; a lane with no source (shifted in
+// from outside its row, or a row left out) sees an id no run has.
+template <int CTRL, int ROWS, int NSD>
+__device__ __forceinline__ void seg_step(uint32_t rid, double (&acc)[NSD]) {
+    const uint32_t orid = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)rid, CTRL, ROWS, 0xf, false);
+    const bool take = orid == rid;
+#pragma unroll
+    for (int c = 0; c < NSD; ++c) {
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(acc[c]), CTRL, ROWS, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(acc[c]), CTRL, ROWS, 0xf, false);
+        if (take) acc[c] = __dadd_rn(__hiloint2double(hi, lo), acc[c]);
+    }
+}
+
+template <int D, int SCHEME, int TILE, int NT, int NSD>
+__device__ __forceinline__ void emit_deposit(const DevInst &in, const uint64_t (*s_val)[TILE], const uint16_t *s_rid,
+                                             double (*s_edge)[2][NSD], uint32_t (*s_erid)[2], int64_t lo, int cnt,
+                                             const uint32_t *run_info, const uint32_t *run_pos, double *run_part) {
+    constexpr int IPT = TILE / NT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t wq0 = (uint32_t)w * 64u * IPT, wq1 = wq0 + 64u * IPT;
+    double carry[NSD];
+#pragma unroll
+    for (int c = 0; c < NSD; ++c) carry[c] = 0.0;
+    uint32_t crid = EDGE_NONE;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t qq = wq0 + 64u * r + lane;
+        const bool valid = qq < (uint32_t)cnt;
+        const uint32_t rid = valid ? (uint32_t)s_rid[qq] : EDGE_NONE;
+        double acc[NSD];
+#pragma unroll
+        for (int c = 0; c < NSD; ++c) acc[c] = 0.0;
+        if (valid) {
+            double xp[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) xp[k] = __longlong_as_double((long long)s_val[k][qq]);
+            deposit_one<D, SCHEME, true, NSD>(in, xp, 0, 1.0, 1u, 1.0, 1.0, false, acc);
+        }
+        // the previous round's last run: continued by this round, or ended there
+        if (crid != EDGE_NONE) {
+            const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)rid, 0);
+            if (r0 == crid) {
+                if (lane == 0)
+#pragma unroll
+                    for (int c = 0; c < NSD; ++c) acc[c] = __dadd_rn(carry[c], acc[c]);
+            } else if (lane == 0) {
+                emit_finish<NSD>(crid, carry, wq0, w, s_edge, s_erid, lo, run_info, run_pos, run_part);
+            }
+        }
+        // segmented inclusive scan across the lanes: shifts by 1, 2, 4, 8
+        // inside rows of 16 lanes, then each row's last lane to the next row
+        // and lane 31 to the upper half (DPP moves: no LDS traffic)
+        seg_step<0x111, 0xf>(rid, acc);   // row_shr:1
+        seg_step<0x112, 0xf>(rid, acc);   // row_shr:2
+        seg_step<0x114, 0xf>(rid, acc);   // row_shr:4
+        seg_step<0x118, 0xf>(rid, acc);   // row_shr:8
+        seg_step<0x142, 0xa>(rid, acc);   // row_bcast:15 into rows 1 and 3
+        seg_step<0x143, 0xc>(rid, acc);   // row_bcast:31 into rows 2 and 3
+        const uint32_t nrid = (uint32_t)__shfl_down((int)rid, 1, 64);
+        if (valid && lane < 63 && nrid != rid)
+            emit_finish<NSD>(rid, acc, wq0, w, s_edge, s_erid, lo, run_info, run_pos, run_part);
+        crid = (uint32_t)__builtin_amdgcn_readlane((int)rid, 63);
+#pragma unroll
+        for (int c = 0; c < NSD; ++c) carry[c] = readlane_f64(acc[c], 63);
+    }
+    if (crid != EDGE_NONE && lane == 0) {   // the wavefront's last run
+        const bool cont = wq1 < (uint32_t)cnt && (uint32_t)s_rid[wq1] == crid;
+        if (!cont) {
+            emit_finish<NSD>(crid, carry, wq0, w, s_edge, s_erid, lo, run_info, run_pos, run_part);
+        } else if (run_start_of(run_info, lo, crid) >= wq0) {
+#pragma unroll
+            for (int c = 0; c < NSD; ++c) s_edge[w][1][c] = carry[c];
+            s_erid[w][1] = crid | EDGE_VALID;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NSD; ++c) s_edge[w][0][c] = carry[c];
+            s_erid[w][0] = crid | EDGE_VALID | EDGE_CONT;
+        }
+    }
+}
+
+// Runs crossing wavefronts: the wavefront a run started in (thread w) adds
+// the pieces of the following wavefronts in order.
+template <int NW, int NSD>
+__device__ __forceinline__ void emit_edges(const double (*s_edge)[2][NSD], const uint32_t (*s_erid)[2], int64_t lo,
+                                           const uint32_t *run_pos, double *run_part, uint32_t *status) {
+    const int w = threadIdx.x;
+    const uint32_t e = s_erid[w][1];
+    if (!(e & EDGE_VALID)) return;
+    const uint32_t r = e & 0xffffu;
+    double sum[NSD];
+#pragma unroll
+    for (int c = 0; c < NSD; ++c) sum[c] = s_edge[w][1][c];
+    for (int w2 = w + 1; w2 < NW; ++w2) {
+        const uint32_t f = s_erid[w2][0];
+        if (!(f & EDGE_VALID) || (f & 0xffffu) != r) {   // cannot happen for a consistent run table
+            atomicOr(status, PIC_DEV_RANGE);
+            break;
+        }
+#pragma unroll
+        for (int c = 0; c < NSD; ++c) sum[c] = __dadd_rn(sum[c], s_edge[w2][0][c]);
+        if (!(f & EDGE_CONT)) break;
+    }
+    double *o = run_part + (int64_t)run_place_of(run_pos, lo, r) * NSD;
+#pragma unroll
+    for (int c = 0; c < NSD; ++c) o[c] = sum[c];
+}
+
 // Emit pass: slot p of tile T writes its pushed state to
 // run_dest[T's run area + rid] + rank.  NT threads cover the TILE slots of a
-// tile.  With STAGE the tile's records are first put in tile-local sorted
-// order (runs one after the other, each run at its start from the run table)
-// through LDS, STAGE columns at a time, so that a wavefront's stores cover
+// tile.  The tile's records are first put in tile-local sorted order (runs
+// one after the other, each run at its start from the run table) through
+// LDS, two columns at a time, so that a wavefront's stores cover
 // consecutive destinations of a few runs instead of a few elements of each of
 // many runs.
-template <int D, int SCHEME, bool REG, bool MULTI, int TILE, int NT, int STAGE>
+//
+// With DEP (2D, regular single trees, uniform charge) the pass deposits as
+// well (paper Sec. 3 step 1).  Once the positions are in LDS in sorted order,
+// wavefront w takes the sorted slots [64 IPT w, 64 IPT (w+1)) in rounds of
+// 64, computes each slot's corner (PIT) or stencil (PIDT) weights and sums
+// them per run with a segmented inclusive scan across the lanes (a fixed
+// tree of lane shuffles; runs are contiguous in sorted order, so equal run
+// ids at both ends of a step mean one segment), the last lane's run carried
+// into the next round.  A run that ends inside the wavefront and started in
+// it is complete: its sum goes to run_part at the run's position among all
+// runs sorted by (key, tile).  A run crossing wavefronts leaves one piece per
+// wavefront; the wavefront it started in adds the later pieces in wavefront
+// order.  No float atomics: every sum has a fixed order.  k_deposit_runs
+// then adds each bin's runs in output order.
+template <int D, int SCHEME, bool REG, bool MULTI, int TILE, int NT, bool DEP>
 __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const uint32_t *meta,
-                                                  const uint32_t *run_dest, const uint32_t *run_info, F64Ptrs out,
+                                                  const uint32_t *run_dest, const uint32_t *run_info,
+                                                  const uint32_t *run_pos, double *run_part, F64Ptrs out,
                                                   Cols extra, int xcd) {
     constexpr int IPT = TILE / NT;
-    constexpr int NS = STAGE > 0 ? STAGE : 1;
+    constexpr int NW = NT / 64;
+    constexpr int NSD = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
+    static_assert(!DEP || (D == 2 && REG && !MULTI), "the writing pass deposits for 2D regular single trees");
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
-    __shared__ uint64_t s_val[STAGE ? NS : 1][STAGE ? TILE : 1];
-    __shared__ uint32_t s_dst[STAGE ? TILE : 1];
+    __shared__ uint64_t s_val[2][TILE];
+    __shared__ uint32_t s_dst[TILE];
     __shared__ uint32_t s_rd[RUN_HEAD], s_ro[RUN_HEAD];
+    __shared__ uint16_t s_rid[DEP ? TILE : 1];
+    __shared__ double s_edge[DEP ? NW : 1][2][DEP ? NSD : 1];   // per wavefront: first piece, last piece
+    __shared__ uint32_t s_erid[DEP ? NW : 1][2];                // their run ids | VALID | CONT
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
     const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
     const int cnt = (int)min((int64_t)TILE, n - lo);
-    if (STAGE)
-        for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
+    for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
+    if (DEP && tid < NW) {
+        s_erid[tid][0] = EDGE_NONE;
+        s_erid[tid][1] = EDGE_NONE;
+    }
     double xv[IPT][D], vv[IPT][D];
     uint32_t mt[IPT], dst[IPT], q[IPT];
     uint32_t bad = 0;
@@ -131,22 +264,22 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         s_ro[tid] = ro0 & 0xffffu;
     }
     __syncthreads();   // run head in LDS, s_dst cleared
-    uint32_t miss = 0;
+    uint32_t miss = 0, rid[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
         dst[j] = ~0u;
         q[j] = ~0u;
+        rid[j] = 0u;
         if (full || p < n) {
-            const uint32_t rid = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u), rank = mt[j] >> 16;
-            const bool head = rid < (uint32_t)RUN_HEAD;
-            const uint32_t d = (head ? s_rd[rid] : run_dest[lo + rid]) + rank;
-            dst[j] = (d < (uint32_t)n && rid == (mt[j] & 0xffffu)) ? d : ~0u;
-            if (STAGE) {
-                const uint32_t qq = (head ? s_ro[rid] : (run_info[lo + rid] & 0xffffu)) + rank;
-                q[j] = qq < (uint32_t)cnt ? qq : ~0u;
-                if (q[j] == ~0u) dst[j] = ~0u;
-            }
+            rid[j] = min(mt[j] & 0xffffu, (uint32_t)TILE - 1u);
+            const uint32_t rank = mt[j] >> 16;
+            const bool head = rid[j] < (uint32_t)RUN_HEAD;
+            const uint32_t d = (head ? s_rd[rid[j]] : run_dest[lo + rid[j]]) + rank;
+            dst[j] = (d < (uint32_t)n && rid[j] == (mt[j] & 0xffffu)) ? d : ~0u;
+            const uint32_t qq = (head ? s_ro[rid[j]] : (run_info[lo + rid[j]] & 0xffffu)) + rank;
+            q[j] = qq < (uint32_t)cnt ? qq : ~0u;
+            if (q[j] == ~0u) dst[j] = ~0u;
             if (dst[j] == ~0u) miss = 1;
         }
     }
@@ -162,66 +295,17 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         push_one<D, SCHEME, REG, false, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
     }
     if (miss) flag_status(t.status, PIC_DEV_RANGE);
-    if (!STAGE) {
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            if (dst[j] == ~0u) continue;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                out.x[k][dst[j]] = xv[j][k];
-                out.v[k][dst[j]] = vv[j][k];
-            }
-        }
-        for (int c = 0; c < extra.n; ++c) {
-            if (extra.bytes[c] == 8) {
-                const uint64_t *src = (const uint64_t *)extra.in[c];
-                uint64_t *o = (uint64_t *)extra.out[c];
-                uint64_t v[IPT];
-#pragma unroll
-                for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
-#pragma unroll
-                for (int j = 0; j < IPT; ++j)
-                    if (dst[j] != ~0u) o[dst[j]] = v[j];
-            } else {
-                const uint32_t *src = (const uint32_t *)extra.in[c];
-                uint32_t *o = (uint32_t *)extra.out[c];
-                uint32_t v[IPT];
-#pragma unroll
-                for (int j = 0; j < IPT; ++j) v[j] = dst[j] != ~0u ? src[base + 64 * j] : 0u;
-#pragma unroll
-                for (int j = 0; j < IPT; ++j)
-                    if (dst[j] != ~0u) o[dst[j]] = v[j];
-            }
-        }
-        return;
-    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j)
-        if (dst[j] != ~0u) s_dst[q[j]] = dst[j];
-    // the 2D state columns, then the extra columns, NS at a time
-    const int ncol = 2 * D + extra.n;
-    for (int c0 = 0; c0 < ncol; c0 += NS) {
-#pragma unroll
-        for (int g = 0; g < NS; ++g) {
-            const int c = c0 + g;
-            if (c >= ncol) break;
-            if (c < 2 * D) {
-#pragma unroll
-                for (int j = 0; j < IPT; ++j)
-                    if (dst[j] != ~0u) s_val[g][q[j]] = __double_as_longlong(c < D ? xv[j][c] : vv[j][c - D]);
-            } else {
-                const int e = c - 2 * D;
-                const bool wide = extra.bytes[e] == 8;
-#pragma unroll
-                for (int j = 0; j < IPT; ++j)
-                    if (dst[j] != ~0u)
-                        s_val[g][q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
-                                              : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
-            }
+        if (dst[j] != ~0u) {
+            s_dst[q[j]] = dst[j];
+            if (DEP) s_rid[q[j]] = (uint16_t)rid[j];
         }
-        __syncthreads();
+    // the state columns (unrolled, so the registers are indexed by
+    // constants), then the extra columns, two at a time
+    auto write_out = [&](int c0, int ncol) {
 #pragma unroll
-        for (int g = 0; g < NS; ++g) {
+        for (int g = 0; g < 2; ++g) {
             const int c = c0 + g;
             if (c >= ncol) break;
             const bool st = c < 2 * D;
@@ -237,7 +321,64 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
                 else ((uint32_t *)o)[d] = (uint32_t)s_val[g][qq];
             }
         }
+    };
+#pragma unroll
+    for (int c0 = 0; c0 < 2 * D; c0 += 2) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int c = c0 + g;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u) s_val[g][q[j]] = __double_as_longlong(c < D ? xv[j][c] : vv[j][c - D]);
+        }
         __syncthreads();
+        if constexpr (DEP) {
+            if (c0 == 0)
+                emit_deposit<D, SCHEME, TILE, NT, NSD>(in0, s_val, s_rid, s_edge, s_erid, lo, cnt, run_info, run_pos,
+                                                       run_part);
+            else if (c0 == 2 && tid < NW)
+                emit_edges<NW, NSD>(s_edge, s_erid, lo, run_pos, run_part, t.status);
+        }
+        write_out(c0, 2 * D);
+        __syncthreads();
+    }
+    const int ncol = 2 * D + extra.n;
+    for (int c0 = 2 * D; c0 < ncol; c0 += 2) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int c = c0 + g;
+            if (c >= ncol) break;
+            const int e = c - 2 * D;
+            const bool wide = extra.bytes[e] == 8;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (dst[j] != ~0u)
+                    s_val[g][q[j]] = wide ? ((const uint64_t *)extra.in[e])[base + 64 * j]
+                                          : (uint64_t)((const uint32_t *)extra.in[e])[base + 64 * j];
+        }
+        __syncthreads();
+        write_out(c0, ncol);
+        __syncthreads();
+    }
+}
+
+// Per bin: the sum of its runs' partials (stayers' runs of all tiles in tile
+// order, then arrivals' runs in tile order: the runs' order in the output),
+// the per-bin partials k_deposit_vertices sums per vertex.
+template <int NS>
+__global__ __launch_bounds__(256) void k_deposit_runs(const uint32_t *list_off, int64_t n_bins,
+                                                      const double *run_part, double *partial) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins; b += stride) {
+        const uint32_t r0 = list_off[2 * b], r1 = list_off[2 * b + 2];
+        double acc[NS];
+#pragma unroll
+        for (int c = 0; c < NS; ++c) acc[c] = 0.0;
+        for (uint32_t r = r0; r < r1; ++r)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) acc[c] = __dadd_rn(acc[c], run_part[(int64_t)r * NS + c]);
+#pragma unroll
+        for (int c = 0; c < NS; ++c) partial[b * NS + c] = acc[c];
     }
 }
 
@@ -253,18 +394,26 @@ struct StepArgs {
     const int64_t *inst_start, *old_start;
     uint32_t n_bins;
     void *stats;      // nullable pic_rebin_stats record
+    bool deposit;     // the writing pass deposits (2D regular single trees, uniform charge)
 };
 
-#define PIC_EMIT(NT)                                                                                          \
-    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, 2>), dim3(tiles), dim3(NT), 0, s, t->dt, \
+#define PIC_EMIT(NT, DEP)                                                                                     \
+    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP>), dim3(tiles), dim3(NT), 0, s, t->dt,  \
                t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,          \
-               (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, a.out, extra, t->tune.xcd_tiles)
+               (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, (const uint32_t *)sc.run_pos,      \
+               sc.run_part, a.out, extra, t->tune.xcd_tiles)
 
 template <int D, int SCH, bool REG, bool MULTI, int TILE>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + TILE - 1) / TILE;
-    if (a.n > 0) {
+    if (a.n > 0 && t->tune.step_fuse) {
+        // counters cleared first; the key pass and the ranking are one kernel
+        launch_prep(a.zero, a.n_zero, nullptr, a.n_bins, a.n, TILE, sc, s);
+        launch_keyrank(t, SCH, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, TILE, sc,
+                       a.stats ? sc.keys : nullptr, s);
+        if (a.stats) (void)launch_rebin_stats(t, SCH, a.old_start, sc.keys, 1, a.n, a.stats, s);
+    } else if (a.n > 0) {
         PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0, s,
                    t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
                    sc.keys, a.zero, a.n_zero);
@@ -273,8 +422,15 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
     }
     launch_step_middle(t, a.n, a.n_bins, sc, new_start, s);
     if (a.n == 0) return;
-    if (t->tune.emit_threads == 512) PIC_EMIT(512);
-    else PIC_EMIT(1024);
+    if constexpr (D == 2 && REG && !MULTI) {
+        if (a.deposit) {
+            if (t->tune.emit_threads == 512) PIC_EMIT(512, true);
+            else PIC_EMIT(1024, true);
+            return;
+        }
+    }
+    if (t->tune.emit_threads == 512) PIC_EMIT(512, false);
+    else PIC_EMIT(1024, false);
 }
 
 template <int D, int SCH>
@@ -301,13 +457,16 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     const int64_t n = in->n;
     const int64_t n_bins = n_bins_of(t, scheme);
     const int tile = RB_THREADS * t->tune.step_ipt;
-    const RebinLayout L = rebin_layout(n, n_bins, tile);
+    const int ns = scheme == PIC_PIT ? 4 : 9;   // 2D deposit slots per run
+    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 ? ns : 0);
     if (scratch_bytes < L.total || scratch_bytes < deposit_scratch_bytes(t, scheme)) return hipErrorInvalidValue;
     char *base = (char *)scratch;
     const RebinScratch sc = bind_scratch(L, base);
-    const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
+    // the fused step's per-call counters: key_cn, the scan state and ticket,
+    // the linked run lists' heads (contiguous in the layout)
+    const int64_t zero_words = (int64_t)((L.key_base - L.key_cn) / 4);
     StepArgs a;
-    a.zero = (uint32_t *)(base + L.key_cnt);
+    a.zero = (uint32_t *)(base + L.key_cn);
     a.n_zero = zero_words;
     // the key pass clears the counters; with no particles there is none
     if (n == 0) launch_prep(a.zero, zero_words, nullptr, n_bins, n, tile, sc, s);
@@ -322,6 +481,7 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     a.old_start = old_start;
     a.n_bins = (uint32_t)n_bins;
     a.stats = stats;
+    a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && t->tune.emit_deposit;
     if (t->dim == 2) {
         if (scheme == PIC_PIT) launch_step_shape<2, 0>(t, a, sc, extra, new_start, s);
         else launch_step_shape<2, 1>(t, a, sc, extra, new_start, s);
@@ -330,7 +490,16 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
         else launch_step_shape<3, 1>(t, a, sc, extra, new_start, s);
     }
     const double *q = q_col >= 0 ? (const double *)extra.out[q_col] : nullptr;
-    return launch_deposit(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);
+    if (!a.deposit || n == 0) return launch_deposit(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);
+    // the writing pass left one partial per run: sum them per bin, then per vertex
+    double *partial = (double *)(base + L.bin_part);
+    const dim3 g(grid_for(n_bins, 256, 1 << 16)), b(256);
+    if (ns == 4) PIC_LAUNCH("deposit_runs", k_deposit_runs<4>, g, b, 0, s, (const uint32_t *)sc.list_off, n_bins,
+                            (const double *)sc.run_part, partial);
+    else PIC_LAUNCH("deposit_runs", k_deposit_runs<9>, g, b, 0, s, (const uint32_t *)sc.list_off, n_bins,
+                    (const double *)sc.run_part, partial);
+    launch_deposit_vertices(t, scheme, true, partial, false, q_uniform, rho, s);
+    return hipGetLastError();
 }
 
 }  // namespace pic

@@ -312,8 +312,8 @@ def test_fused_step_matches_oracle(name, scheme, kind):
     assert t.status_sync() == 0
 
 
-STEP_FORMS = [dict(emit_threads=nt, xcd_tiles=x, step_tile=tl) for nt in (1024, 512) for x in (1, 0)
-              for tl in (2048, 1024)]
+STEP_FORMS = [dict(step_fuse=f, emit_threads=nt, xcd_tiles=x, step_tile=tl, emit_deposit=dep) for f in (1, 0)
+              for nt in (1024, 512) for x in (1, 0) for tl in (2048, 1024) for dep in (1, 0)]
 
 
 @pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
@@ -351,9 +351,10 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
 
 
 @pytest.mark.parametrize("tiles", [80, 160])
+@pytest.mark.parametrize("step_fuse", [1, 0])
 @pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_fused_step_with_overfull_key_lists(step_tile, scheme, tiles):
+def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, scheme, tiles):
     """Every tile sends particles to every bin of a 3x3 tree, so each key
     collects about as many runs as there are tiles: 80 take the placement by
     counting (more than a wavefront sorts), 160 overflow the direct list into
@@ -362,6 +363,7 @@ def test_fused_step_with_overfull_key_lists(step_tile, scheme, tiles):
     saved = pic.tuning()
     try:
         pic.tune("step_tile", step_tile)
+        pic.tune("step_fuse", step_fuse)
         rng = np.random.default_rng(31)
         spec = W.regular_tree(2, 1)
         n = tiles * 2048 + 77
@@ -385,7 +387,8 @@ def test_fused_step_with_overfull_key_lists(step_tile, scheme, tiles):
             pic.tune(k, v)
 
 
-MANY_RUN_FORMS = [dict(), dict(emit_threads=512), dict(step_tile=1024), dict(step_tile=1024, emit_threads=512)]
+MANY_RUN_FORMS = [dict(), dict(emit_threads=512), dict(step_tile=1024), dict(step_tile=1024, emit_threads=512),
+                  dict(step_fuse=0), dict(step_fuse=0, step_tile=1024)]
 
 
 @pytest.mark.parametrize("knobs", MANY_RUN_FORMS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()) or "default")
@@ -568,3 +571,51 @@ def test_forest_stats_match_oracle_per_instance_sum():
         torch.cuda.synchronize()
         assert pic.read_stats(stats) == want
         assert t.status_sync() == 0
+
+
+@pytest.mark.parametrize("emit_threads", [1024, 512])
+@pytest.mark.parametrize("step_tile", [2048, 1024])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1023, 2048, 2049, 9000])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_writing_pass_deposit_with_long_runs_and_ragged_tiles(scheme, n, step_tile, emit_threads):
+    """The writing pass's deposit on a regular 2D tree: half the particles
+    sit in one cell with slow velocities, so each tile holds a run of stayers
+    that spans several wavefronts (and whole tiles), the rest are spread over
+    the tree; ragged last tiles and sets smaller than a wavefront.  The
+    charge equals the oracle's within 1e-12 per vertex, the state bit for
+    bit, and the separate deposit gives the same charge to rounding."""
+    dev = _dev()
+    saved = pic.tuning()
+    try:
+        pic.tune("step_tile", step_tile)
+        pic.tune("emit_threads", emit_threads)
+        rng = np.random.default_rng(n * 3 + scheme)
+        spec = W.regular_tree(2, 2)
+        o = oracle.OracleTree(spec)
+        half = n // 2
+        x = np.concatenate([0.40 + 0.02 * rng.random((2, half)), rng.random((2, n - half))], axis=1)
+        v = np.concatenate([0.001 * rng.standard_normal((2, half)), 0.3 * rng.standard_normal((2, n - half))], axis=1)
+        E = W.random_field(rng, 2, o.n_vertices, 0.02)
+        rhos = []
+        for dep in (1, 0):
+            pic.tune("emit_deposit", dep)
+            t = _tree(spec)
+            st = pic.Stepper(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+            st.initial_sort()
+            xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+            for it in range(2):
+                st.step_fused(torch.tensor(E, device=dev), -0.5, 0.5, q_uniform=-1.0 / n)
+                r = oracle.step(o, xs, vs, E, -0.5, 0.5, start, scheme, None, -1.0 / n)
+                torch.cuda.synchronize()
+                ids = ids[r["perm"]]
+                assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+                assert np.array_equal(st.ids.cpu().numpy(), ids)
+                assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+                _check_rho(st.rho.cpu().numpy(), r["rho"])
+                xs, vs, start = r["x"], r["v"], r["bin_start"]
+            rhos.append(st.rho.cpu().numpy())
+            assert t.status_sync() == 0
+        assert np.allclose(rhos[0], rhos[1], rtol=1e-13, atol=0.0)
+    finally:
+        for k, val in saved.items():
+            pic.tune(k, val)
