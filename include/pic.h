@@ -414,6 +414,9 @@ pic_status pic_profile_only(const char *name);
  *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);
  *   "step_fuse"     1 = pic_step's key pass and tile ranking run as one kernel, 0 = as
  *                   a key pass that writes the keys and a ranking pass (default 0);
+ *   "group_match"   pic_step's ranking pass (step_fuse 0): 1 = lanes with equal keys
+ *                   found by wavefront ballots, one table access per distinct key;
+ *                   0 = every lane tags and masks its table slot (default 0);
  *   "emit_deposit"  1 = for 2D single trees whose instances are regular and a uniform
  *                   charge, pic_step's writing pass sums each run's weights while
  *                   the run is in LDS and the deposit only adds runs per bin; 0 = the

@@ -681,7 +681,7 @@ static void step_passes_f32(const pic_tree *t, const F32Ptrs &P, const F32Ptrs &
                t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
                TILE, sc.keys, (const uint32_t *)sc.wave_bin);
     if (stats) (void)launch_rebin_stats(t, SCH, old_start, sc.keys, 1, n, stats, s);
-    launch_group(sc.keys, n, TILE, sc, s);
+    launch_group(sc.keys, n, TILE, t->tune.group_match != 0, sc, s);
     launch_step_middle(t, n, n_bins, sc, new_start, s);
     PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024>), dim3(tiles), dim3(1024), 0, s, t->dt,
                t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,

@@ -117,7 +117,7 @@ void launch_keyrank(const pic_tree *t, int scheme, const F64Ptrs &P, int64_t n, 
                     const double *qa, const double *da, const int64_t *inst_start, const int64_t *old_start,
                     uint32_t n_bins, int tile, const RebinScratch &sc, uint32_t *keys_out, hipStream_t s);
 // The tile ranking of the fused step over keys in memory (pic_rank.hip).
-void launch_group(const uint32_t *keys, int64_t n, int tile, const RebinScratch &sc, hipStream_t s);
+void launch_group(const uint32_t *keys, int64_t n, int tile, bool match, const RebinScratch &sc, hipStream_t s);
 // Per-vertex sums of the deposit's per-bin partials (pic_kernels.hip); `reg`
 // selects the arithmetic enumeration of regular trees.
 void launch_deposit_vertices(const pic_tree *t, int scheme, bool reg, const double *partial, bool use_q,

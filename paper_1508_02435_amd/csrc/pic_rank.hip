@@ -355,6 +355,37 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_group(const uint32_t *keys,
     tile_rank<IPT>(S, key, tile, lo, sc, meta);
 }
 
+// Group pass by matching: the same ranks as k_step_group (slot order), with
+// one LDS access per distinct key of a wavefront round instead of several per
+// particle (match_rank).
+template <int IPT>
+__global__ __launch_bounds__(RB_THREADS) void k_step_group_match(const uint32_t *keys, int64_t n, RebinScratch sc,
+                                                                uint32_t *meta, int xcd) {
+    using RS = RankShape<IPT>;
+    __shared__ MatchSmem<IPT> S;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, xcd);
+    const int64_t lo = tile * RS::TILE;
+    match_clear<IPT>(S);
+    const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
+    uint32_t key[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) key[j] = base + 64 * j < n ? keys[base + 64 * j] : ~0u;
+    __syncthreads();   // table cleared
+    uint32_t res[IPT];   // per particle: table slot | rank << 16
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) res[j] = match_rank<IPT>(S, key[j], w);
+    __syncthreads();
+    tile_compact<IPT>(S, tile, lo, sc);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t r = res[j];
+        if (r == ~0u) continue;
+        const uint32_t hs = r & 0xffffu;
+        meta[base + 64 * j] = S.key[hs] | (((uint32_t)S.wc[w][hs] + (r >> 16)) << 16);
+    }
+}
+
 // Fused step, middle.  Scan: each block of SP_THREADS threads scans the
 // (count, runs) pairs of SP_KEYS keys; its first wavefront publishes the
 // block's aggregate and looks back over up to 64 predecessors at a time (one
@@ -601,13 +632,21 @@ void launch_keyrank(const pic_tree *t, int scheme, const F64Ptrs &P, int64_t n, 
 #undef PIC_KR
 }
 
-void launch_group(const uint32_t *keys, int64_t n, int tile, const RebinScratch &sc, hipStream_t s) {
+void launch_group(const uint32_t *keys, int64_t n, int tile, bool match, const RebinScratch &sc, hipStream_t s) {
     const int64_t tiles = (n + tile - 1) / tile;
     if (n == 0) return;
-    if (tile == 1024)
+    if (match) {
+        if (tile == 1024)
+            PIC_LAUNCH("step_group", (k_step_group_match<4>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta,
+                       0);
+        else
+            PIC_LAUNCH("step_group", (k_step_group_match<8>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta,
+                       0);
+    } else if (tile == 1024) {
         PIC_LAUNCH("step_group", (k_step_group<4>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta, 0);
-    else
+    } else {
         PIC_LAUNCH("step_group", (k_step_group<8>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta, 0);
+    }
 }
 
 // The middle of the fused step: scan, then placement from the per-key lists.

@@ -418,7 +418,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
                    t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
                    sc.keys, a.zero, a.n_zero);
         if (a.stats) (void)launch_rebin_stats(t, SCH, a.old_start, sc.keys, 1, a.n, a.stats, s);
-        launch_group(sc.keys, a.n, TILE, sc, s);
+        launch_group(sc.keys, a.n, TILE, t->tune.group_match != 0, sc, s);
     }
     launch_step_middle(t, a.n, a.n_bins, sc, new_start, s);
     if (a.n == 0) return;

@@ -312,8 +312,9 @@ def test_fused_step_matches_oracle(name, scheme, kind):
     assert t.status_sync() == 0
 
 
-STEP_FORMS = [dict(step_fuse=f, emit_threads=nt, xcd_tiles=x, step_tile=tl, emit_deposit=dep) for f in (1, 0)
-              for nt in (1024, 512) for x in (1, 0) for tl in (2048, 1024) for dep in (1, 0)]
+STEP_FORMS = [dict(step_fuse=f, group_match=gm, emit_threads=nt, xcd_tiles=x, step_tile=tl, emit_deposit=dep)
+              for f, gm in ((1, 0), (0, 0), (0, 1)) for nt in (1024, 512) for x in (1, 0) for tl in (2048, 1024)
+              for dep in (1, 0)]
 
 
 @pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
@@ -351,10 +352,10 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
 
 
 @pytest.mark.parametrize("tiles", [80, 160])
-@pytest.mark.parametrize("step_fuse", [1, 0])
+@pytest.mark.parametrize("step_fuse,group_match", [(1, 0), (0, 1), (0, 0)])
 @pytest.mark.parametrize("step_tile", [2048, 1024])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, scheme, tiles):
+def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, group_match, scheme, tiles):
     """Every tile sends particles to every bin of a 3x3 tree, so each key
     collects about as many runs as there are tiles: 80 take the placement by
     counting (more than a wavefront sorts), 160 overflow the direct list into
@@ -364,6 +365,7 @@ def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, scheme, tiles)
     try:
         pic.tune("step_tile", step_tile)
         pic.tune("step_fuse", step_fuse)
+        pic.tune("group_match", group_match)
         rng = np.random.default_rng(31)
         spec = W.regular_tree(2, 1)
         n = tiles * 2048 + 77
@@ -388,7 +390,8 @@ def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, scheme, tiles)
 
 
 MANY_RUN_FORMS = [dict(), dict(emit_threads=512), dict(step_tile=1024), dict(step_tile=1024, emit_threads=512),
-                  dict(step_fuse=0), dict(step_fuse=0, step_tile=1024)]
+                  dict(step_fuse=1), dict(step_fuse=1, step_tile=1024), dict(group_match=1),
+                  dict(group_match=1, step_tile=1024)]
 
 
 @pytest.mark.parametrize("knobs", MANY_RUN_FORMS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()) or "default")
