@@ -33,6 +33,10 @@ PIT, PIDT = 0, 1
 STATS_LEVELS = 20   # entries of the lift-count histogram
 
 
+# A prebuilt library to load instead (the sanitized build of the CPU test run).
+_LIB_OVERRIDE = os.environ.get("PIC_ORACLE_LIB")
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -41,6 +45,18 @@ def build(force: bool = True) -> str:
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_sanitized(out: str) -> str:
+    """Compile the oracle with clang under AddressSanitizer and
+    UndefinedBehaviorSanitizer (same arithmetic flags), for a process that
+    preloads clang's ASan runtime."""
+    clang = os.environ.get("CLANG", "/opt/rocm/llvm/bin/clang")
+    subprocess.check_call([clang, "-O1", "-g", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                           "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-shared-libsan", "-fPIC", "-shared", "-o", out, _SRC,
+                           "-lm"])
+    return out
 
 
 _lib = None
@@ -58,7 +74,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        _lib = load(_LIB)
+        _lib = load(_LIB_OVERRIDE or _LIB)
     return _lib
 
 

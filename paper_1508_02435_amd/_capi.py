@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpic.so")
+# PIC_LIBPIC names another build of the same library (the sanitized one of
+# the CPU test run)
+LIB_PATH = os.environ.get("PIC_LIBPIC") or os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_E_ARG, PIC_E_SCRATCH, PIC_E_CAPACITY, PIC_E_NONFINITE, PIC_E_TREE, PIC_E_HIP, PIC_E_RANGE, \
     PIC_E_STATE = range(9)

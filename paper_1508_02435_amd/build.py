@@ -30,9 +30,20 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c", "-o", obj, os.path.join(CSRC, src)]
+# host code only: AddressSanitizer and UndefinedBehaviorSanitizer (every
+# option behind -Xarch_host, so the device code is built as always)
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+SAN_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-shared-libsan"]
+
+
+def _compile(src: str, verbose: bool, sanitize: bool = False) -> str:
+    odir = OBJ + "_san" if sanitize else OBJ
+    obj = os.path.join(odir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *(SAN_HOST if sanitize else []), "-I", os.path.join(HERE, "..", "include"), "-c", "-o",
+           obj, os.path.join(CSRC, src)]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,22 +53,27 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 0, sanitize: bool = False) -> str:
+    """Build libpic.so; with ``sanitize`` build libpic_san.so instead, whose
+    host code runs under AddressSanitizer and UndefinedBehaviorSanitizer
+    (load it with PIC_LIBPIC in a process that preloads clang's ASan
+    runtime)."""
+    os.makedirs(OBJ + "_san" if sanitize else OBJ, exist_ok=True)
+    out = os.path.join(HERE, "libpic_san.so") if sanitize else LIB
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda s: _compile(s, verbose, sanitize), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *(SAN_LINK if sanitize else []), "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed linking libpic.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv[1:]))
