@@ -14,12 +14,16 @@ Paper sections followed (see the C file header for the readings):
   Sec. 5.1 PIT: each particle held by the leaf covering it (Theorem 1).
   Sec. 5.2 PIDT: each particle held by the vertex whose dual cell covers it
            (Theorem 2).
+  Sec. 6   the particle-handling benchmark: free streaming with periodic or
+           reflecting walls and artificial flops; the ppc-driven dynamic
+           refinement and coarsening of the tree.
   Sec. 6.1 lifts per particle and step (re-bin statistics).
   App. A   Langmuir-wave units and the Bohm-Gross relation.
 """
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import os
 import subprocess
 
@@ -30,6 +34,7 @@ _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB = os.path.join(_HERE, "_pic_oracle.so")
 
 PIT, PIDT = 0, 1
+PERIODIC, REFLECT = 0, 1
 STATS_LEVELS = 20   # entries of the lift-count histogram
 
 
@@ -95,6 +100,8 @@ def _declare(L):
     L.orc_weights.argtypes = [vp, i64, vp, vp, vp]
     L.orc_gather_push.restype = i32
     L.orc_gather_push.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, vp, vp, i32]
+    L.orc_free_stream.restype = i32
+    L.orc_free_stream.argtypes = [vp, i64, vp, vp, dbl, i32, i32, vp, i32]
     L.orc_rebin.restype = i32
     L.orc_rebin.argtypes = [i64, i64, vp, vp, vp, vp]
     L.orc_deposit.restype = i32
@@ -206,6 +213,18 @@ class OracleTree:
             raise ValueError("oracle: position outside [0,1)")
         return x, v, ep, bins
 
+    def free_stream(self, x, v, dt, boundary=REFLECT, flops=0, scheme=PIT):
+        """One free-streaming move (no field): returns (x', v', new_bin)
+        without touching the inputs."""
+        x = np.array(x, np.float64, order="C", copy=True)
+        v = np.array(v, np.float64, order="C", copy=True)
+        n = x.shape[1]
+        bins = np.zeros(n, np.int32)
+        if self._L.orc_free_stream(self._h, n, _p(x), _p(v), float(dt), int(boundary), int(flops), _p(bins),
+                                   int(scheme)):
+            raise ValueError("oracle: position outside [0,1) or a move longer than the box")
+        return x, v, bins
+
     def deposit(self, x, q=None, q_uniform=0.0):
         x = np.ascontiguousarray(x, np.float64)
         n = x.shape[1]
@@ -267,6 +286,85 @@ def step(tree: OracleTree, x, v, E, qmdt, dt, bin_start, scheme=PIT, q=None, q_u
 
 # ---------------------------------------------------------------------------
 # Support outside the hot path (regular periodic trees only): Poisson + field
+# ---------------------------------------------------------------------------
+# ppc-driven dynamic adaptivity (paper Sec. 6 setup; Sec. 5 opening remark)
+# ---------------------------------------------------------------------------
+
+def _cells_of(spec):
+    """Existing cells per level: a set of integer coordinate tuples, and of
+    those the refined ones, read from the masks (lexicographic, axis 0
+    fastest)."""
+    d = spec.dim
+    exist = [{(0,) * d}]
+    refined = []
+    for l in range(spec.max_level):
+        n = 3 ** l
+        m = np.asarray(spec.refine[l]).ravel()
+        ref = {a for a in exist[l] if m[sum(a[k] * n ** k for k in range(d))]}
+        refined.append(ref)
+        nxt = set()
+        for a in ref:
+            for c in itertools.product(range(3), repeat=d):
+                nxt.add(tuple(3 * a[k] + c[k] for k in range(d)))
+        exist.append(nxt)
+    refined.append(set())
+    return exist, refined
+
+
+def adapt(spec, x, ppc: int, max_level: int):
+    """One adaptation of the tree to the particles ``x`` (dim, n): a leaf
+    holding more than ``ppc`` particles is refined (below ``max_level``); a
+    refined cell other than the root whose children are all leaves holding
+    together at most ``ppc`` particles loses its children.  Returns the new
+    spec; refine masks are 0 for every cell that does not exist."""
+    import workloads as W
+    d, L, S = spec.dim, spec.max_level, 3 ** spec.max_level
+    exist, refined = _cells_of(spec)
+    # particles per leaf, by the leaf box holding the finest cell of fl(x S)
+    I = np.minimum(np.floor(np.asarray(x, np.float64) * S), S - 1).astype(np.int64)
+    count = {}
+    for l in range(L + 1):
+        leaves = exist[l] - refined[l]
+        if not leaves:
+            continue
+        s = 3 ** (L - l)
+        a = I // s
+        for p in range(I.shape[1]):
+            key = tuple(int(a[k, p]) for k in range(d))
+            if key in leaves:
+                count[(l, key)] = count.get((l, key), 0) + 1
+    new_ref = [set(r) for r in refined]
+    for l in range(L + 1):
+        for a in exist[l] - refined[l]:
+            if l < max_level and count.get((l, a), 0) > ppc:
+                while len(new_ref) <= l:
+                    new_ref.append(set())
+                new_ref[l].add(a)
+    for l in range(1, L):
+        for a in refined[l]:
+            kids = [tuple(3 * a[k] + c[k] for k in range(d)) for c in itertools.product(range(3), repeat=d)]
+            if any(kk in refined[l + 1] for kk in kids):
+                continue
+            if sum(count.get((l + 1, kk), 0) for kk in kids) <= ppc:
+                new_ref[l].discard(a)
+    # the new tree: cells reached from the root through refined cells
+    levels = []
+    live = {(0,) * d}
+    l = 0
+    while l < len(new_ref):
+        ref = {a for a in live if a in new_ref[l]}
+        if not ref:
+            break
+        n = 3 ** l
+        m = np.zeros(n ** d, np.uint8)
+        for a in ref:
+            m[sum(a[k] * n ** k for k in range(d))] = 1
+        levels.append(m)
+        live = {tuple(3 * a[k] + c[k] for k in range(d)) for a in ref for c in itertools.product(range(3), repeat=d)}
+        l += 1
+    return W.TreeSpec(d, len(levels), levels)
+
+
 # ---------------------------------------------------------------------------
 
 def _grid(a, dim, n):

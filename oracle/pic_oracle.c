@@ -472,6 +472,61 @@ int orc_gather_push(void *h, int64_t n, double *x, double *v, const double *E,
     return 0;
 }
 
+/* ---------------------------------------------------------------- free streaming */
+/* The particle-handling benchmark of the paper's results section (Sec. 6,
+   setup): no field and no particle-grid interplay; every particle moves
+   x <- x + v dt per axis, then
+     boundary 0 (periodic):   x <- x - floor(x), 1.0 -> 0.0 (as in the push);
+     boundary 1 (reflecting): below 0 the position is mirrored at 0 (x -> -x),
+       at or above 1 at 1 (x -> 2 - x), and that velocity component changes
+       sign; a particle mirrored exactly onto 1 is put at the largest double
+       below 1.
+   A move that a single reflection cannot bring back (|v dt| >= 1 towards a
+   wall) is an error (-1).  `flops` artificial floating-point operations per
+   particle move (the paper's 0 to 4096) are carried out and discarded.
+   bin (nullable): new bin per particle for `scheme`. */
+static volatile double orc_flop_sink;
+
+int orc_free_stream(void *h, int64_t n, double *x, double *v, double dt, int boundary, int flops,
+                    int32_t *bin, int scheme)
+{
+    otree *t = (otree *)h;
+    int nc = 1 << t->dim;
+    double sink = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        for (int j = 0; j < t->dim; ++j) {
+            double vj = v[j * n + p];
+            double xj = x[j * n + p] + vj * dt;
+            if (boundary == 0) {
+                xj = xj - floor(xj);
+                if (xj == 1.0) xj = 0.0;
+            } else if (xj < 0.0) {
+                xj = -xj;
+                vj = -vj;
+                if (!(xj < 1.0)) return -1;
+            } else if (xj >= 1.0) {
+                xj = 2.0 - xj;
+                vj = -vj;
+                if (xj < 0.0) return -1;
+                if (xj == 1.0) xj = nextafter(1.0, 0.0);
+            }
+            if (!(xj >= 0.0 && xj < 1.0)) return -1;
+            v[j * n + p] = vj;
+            x[j * n + p] = xj;
+        }
+        double a = x[p];
+        for (int f = 0; f < flops / 2; ++f) a = a * 0.5 + 0.25;
+        sink += a;
+        if (bin) {
+            oloc q;
+            if (locate_one(t, x, n, p, &q)) return -1;
+            bin[p] = scheme == 0 ? q.leaf : t->leaf_pidt[(int64_t)q.leaf * nc + owner_corner(t, &q)];
+        }
+    }
+    orc_flop_sink = sink;
+    return 0;
+}
+
 /* ---------------------------------------------------------------- re-bin */
 /* Stable re-bin.  new_bin: n bins in [0,n_bins).  old_start: n_bins+1 segment
    offsets of the input order, or NULL when the input is unsorted (then every

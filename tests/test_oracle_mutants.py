@@ -14,6 +14,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_paper_workload as PW
 import test_oracle_pins as P
 import test_oracle_stats as ST
 import workloads as W
@@ -39,9 +40,9 @@ MUTANTS = {
                                "const double *Ej = E;"),
     "push_kick_sign": ("double vj = v[j * n + p] + qmdt * e;",
                        "double vj = v[j * n + p] - qmdt * e;"),
-    "push_drift_old_velocity": ("double xj = x[j * n + p] + vj * dt;",
-                                "double xj = x[j * n + p] + v[j * n + p] * dt;"),
-    "wrap_keeps_one": ("if (xj == 1.0) xj = 0.0;", ""),
+    "push_drift_old_velocity": ("qmdt * e;\n            double xj = x[j * n + p] + vj * dt;",
+                                "qmdt * e;\n            double xj = x[j * n + p] + v[j * n + p] * dt;"),
+    "wrap_keeps_one": ("if (xj == 1.0) xj = 0.0;\n            v[j * n + p] = vj;", "v[j * n + p] = vj;"),
     "rebin_arrivals_first": ("fill_stay[b] = acc;\n        fill_move[b] = acc + cnt_stay[b];",
                              "fill_move[b] = acc;\n        fill_stay[b] = acc + cnt_move[b];"),
     "deposit_corner_transposed": ("double term = qp * w[c];", "double term = qp * w[c ^ 1];"),
@@ -54,6 +55,11 @@ MUTANTS = {
     "stats_lifts_from_new_level": ("const int lifts = l0 - m;", "const int lifts = l1 - m;"),
     "stats_dual_cells_unshifted": ("a[k] = (bk + (nl - 1) / 2) % nl;", "a[k] = bk % nl;"),
     "stats_tunnel_not_periodic": ("if (t->S - d < d) d = t->S - d;", ""),
+    "reflect_at_zero_keeps_velocity": ("xj = -xj;\n                vj = -vj;", "xj = -xj;"),
+    "reflect_at_one_wraps": ("xj = 2.0 - xj;", "xj = xj - 1.0;"),
+    "landing_on_one_not_moved_inside": ("if (xj == 1.0) xj = nextafter(1.0, 0.0);", ""),
+    "stream_drift_sign": ("double xj = x[j * n + p] + vj * dt;\n            if (boundary == 0) {",
+                          "double xj = x[j * n + p] - vj * dt;\n            if (boundary == 0) {"),
 }
 
 # fast pins, cheapest first; a mutant must make at least one of them fail
@@ -76,6 +82,8 @@ PINS = [
     lambda: ST.test_hand_computed_lifts_on_a_9x9_tree(),
     lambda: ST.test_stats_match_the_lift_mechanism("disc2d_1_3", oracle.PIT, 4),
     lambda: ST.test_stats_match_the_lift_mechanism("reg2d_L2", oracle.PIDT, 4),
+    lambda: PW.test_reflection_hand_cases(),
+    lambda: PW.test_reflecting_stream_is_the_folded_straight_line(),
 ]
 
 
@@ -113,3 +121,36 @@ def test_pins_catch_mutant(name, workdir):
     finally:
         oracle._lib = saved
     assert caught is not None, f"no pin catches mutant {name}"
+
+
+# Slips in the adaptation rule (Python): the function's source with one
+# change, run against the adaptation pins.
+ADAPT_MUTANTS = {
+    "refine_at_ppc": ("count.get((l, a), 0) > ppc", "count.get((l, a), 0) >= ppc"),
+    "coarsen_only_below_ppc": (") <= ppc:", ") < ppc:"),
+    "root_coarsened": ("for l in range(1, L):", "for l in range(0, L):"),
+    "no_level_cap": ("if l < max_level and count", "if count"),
+    "coarsen_despite_refined_child": ("if any(kk in refined[l + 1] for kk in kids):\n                continue", ""),
+}
+ADAPT_PINS = [PW.test_overfull_leaf_is_refined_once, PW.test_underfull_children_are_coarsened,
+              PW.test_cell_with_a_refined_child_is_not_coarsened,
+              lambda adapt: PW.test_repeated_adaptation_reaches_the_ppc_fixed_point(2, "subbox", adapt=adapt)]
+
+
+@pytest.mark.parametrize("name", sorted(ADAPT_MUTANTS))
+def test_pins_catch_adapt_mutant(name):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.adapt))
+    old, new = ADAPT_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), ns)
+    caught = False
+    for pin in ADAPT_PINS:
+        try:
+            pin(adapt=ns["adapt"])
+        except (AssertionError, ValueError, pytest.fail.Exception):
+            caught = True
+            break
+    assert caught, f"no pin catches mutant {name}"
