@@ -65,6 +65,10 @@ typedef int32_t pic_status;
 #define PIC_F64 0          /* x, v in FP64 domain units */
 #define PIC_F32_OFFSET 1   /* FP32 offsets within the leaf, FP32 velocity in cells/step */
 
+/* Walls of the unit box for free streaming (pic_free_stream). */
+#define PIC_PERIODIC 0     /* x wraps into [0,1) as in the push */
+#define PIC_REFLECTING 1   /* x is mirrored at the wall, that velocity component negated */
+
 typedef struct pic_tree pic_tree;   /* opaque host object */
 
 /* ------------------------------------------------------------------ tree */
@@ -438,6 +442,69 @@ int64_t pic_tune_get(const char *name);
 pic_status pic_tree_tune_set(pic_tree *tree, const char *name, int64_t value);
 int64_t pic_tree_tune_get(const pic_tree *tree, const char *name);
 int32_t pic_profile_read(pic_kernel_time *out, int32_t max_entries);
+
+/* ------------------------------------------- particle-handling benchmark
+ *
+ * The workload of the paper's results section (Sec. 6 setup): the field
+ * solve and the particle-grid coupling are left out, every particle streams
+ * freely, the walls reflect, a fixed number of artificial flops can be
+ * imposed on every move, and the tree follows the particles: a leaf holding
+ * more than ppc particles is refined, children that together hold at most
+ * ppc are removed.  A step is pic_free_stream, then pic_rebin (whose
+ * statistics give the lifts per particle, Sec. 6.1); an adaptation is
+ * pic_leaf_counts (or the bin offsets of a PIT-sorted set), pic_tree_adapt,
+ * pic_tree_create on the returned masks, then pic_locate and pic_rebin of
+ * the particles against the new tree (the paper's remark in Sec. 5 that
+ * added and removed nodes re-sort particles by the same mechanism).
+ */
+
+/*
+ * Free streaming, in place: per axis x <- x + v dt, then the wall rule:
+ *   PIC_PERIODIC    x <- x - floor(x), 1.0 -> 0.0;
+ *   PIC_REFLECTING  below 0: x <- -x; at or above 1: x <- 2 - x; either way
+ *                   v <- -v for that axis; a landing exactly on 1 is put at
+ *                   the largest double below 1.
+ * A move that one mirror cannot bring back into [0,1) (|v dt| >= 1 towards
+ * a wall) or a non-finite value sets PIC_E_RANGE / PIC_E_NONFINITE in the
+ * status word (the particle is clamped into the box).  `flops` artificial
+ * floating-point operations (a dependent multiply-add chain whose result is
+ * discarded; even values, 0 to 2^20) are carried out per particle.  The new
+ * bin of every particle under `scheme` is written to bin_dev (n uint32).
+ * dt for a single tree; per instance from params->dt_dev when set (params
+ * may be NULL; its qmdt_dev is ignored).  FP64 form only (PIC_E_ARG
+ * otherwise).  x and v change bit-identically to a serial IEEE evaluation
+ * of the same formulas.
+ */
+pic_status pic_free_stream(const pic_tree *tree, int32_t scheme, int32_t precision, pic_particles *p,
+                           double dt, const pic_push_params *params, int32_t boundary, int32_t flops,
+                           uint32_t *bin_dev, void *stream);
+
+/*
+ * Particles per leaf: count_dev (device, forest-wide leaf count entries of
+ * uint64) is overwritten with the number of particles of p whose position
+ * lies in each leaf (the PIT bin, Theorem 1).  Any order of p.  For a set
+ * sorted into PIT bins the bin offsets give the same numbers.
+ */
+pic_status pic_leaf_counts(const pic_tree *tree, const pic_particles *p, uint64_t *count_dev, void *stream);
+
+/*
+ * One ppc-driven adaptation of a single tree (host only, synchronous):
+ *   - a leaf whose count exceeds ppc is refined if its level is below
+ *     max_level;
+ *   - a refined cell other than the root whose 3^d children are all leaves
+ *     (none of them refined by the rule above) holding together at most ppc
+ *     particles loses its children.
+ * leaf_count: host, one int64 per leaf in leaf-rank order.  The result is
+ * written as the refine masks pic_tree_create takes (levels 0 .. new
+ * max_level-1, (3^l)^d bytes each, 1 = refined; 0 for every cell that does
+ * not exist): *new_max_level and *masks_len (bytes) are always set; masks
+ * may be NULL with masks_cap 0 to ask for the size, and PIC_E_CAPACITY is
+ * returned when masks_cap is below *masks_len.  One rule application per
+ * call (an overfull leaf gains one level per call).  PIC_E_ARG for forests,
+ * negative ppc or a max_level outside the tree limits.
+ */
+pic_status pic_tree_adapt(const pic_tree *tree, const int64_t *leaf_count, int64_t ppc, int32_t max_level,
+                          uint8_t *masks, size_t masks_cap, size_t *masks_len, int32_t *new_max_level);
 
 #ifdef __cplusplus
 }

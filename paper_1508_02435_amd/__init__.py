@@ -51,6 +51,19 @@ def _stream(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+class RefineMasks:
+    """A tree description as pic_tree_create takes it: refine flags per
+    level (``refine[l]``, (3^l)^dim bytes, lexicographic, axis 0 fastest)."""
+
+    def __init__(self, dim: int, max_level: int, refine):
+        self.dim, self.max_level, self.refine = dim, max_level, list(refine)
+
+    def masks_concat(self):
+        if not self.refine:
+            return np.zeros(0, np.uint8)
+        return np.ascontiguousarray(np.concatenate([np.asarray(m, np.uint8).ravel() for m in self.refine]))
+
+
 class Tree:
     """A forest of spacetrees (one or more instances of the same dimension).
 
@@ -66,6 +79,7 @@ class Tree:
         levels = np.array([s.max_level for s in specs], np.int32)
         masks = np.concatenate([s.masks_concat() for s in specs] + [np.zeros(1, np.uint8)])
         self._masks = np.ascontiguousarray(masks)
+        self.specs = list(specs)
         h = C.c_void_p()
         check(lib().pic_tree_create(dim, len(specs), levels.ctypes.data_as(C.c_void_p),
                                     self._masks.ctypes.data_as(C.c_void_p), C.byref(h)), "pic_tree_create")
@@ -245,6 +259,64 @@ def gather_push(tree: Tree, scheme: int, x, v, E, qmdt: float, dt: float, bin_ou
                                 C.c_void_p(_stream(stream))), "pic_gather_push")
 
 
+def free_stream(tree: Tree, scheme: int, x, v, dt: float, boundary: int, flops: int, bin_out, inst_start=None,
+                dt_dev=None, stream=None):
+    """In-place free-streaming move of an FP64 set (no field), periodic or
+    reflecting walls, ``flops`` artificial operations per move; writes the
+    new bins to bin_out."""
+    n = x.shape[1]
+    _check_soa(x, tree.dim, n, "float64", "x")
+    _check_soa(v, tree.dim, n, "float64", "v")
+    _check_vec(bin_out, n, "bin_out")
+    _check_inst(tree, inst_start)
+    if dt_dev is not None:
+        _check_vec(dt_dev, tree.n_inst, "per-instance dt")
+    P = _particles(n, x=x, v=v, inst_start=inst_start)
+    pp = _capi.PushParams(None, _ptr(dt_dev))
+    check(lib().pic_free_stream(tree.handle, scheme, F64, C.byref(P), float(dt), C.byref(pp), int(boundary),
+                                int(flops), C.c_void_p(_ptr(bin_out)), C.c_void_p(_stream(stream))),
+          "pic_free_stream")
+
+
+def leaf_counts(tree: Tree, x, count_out, inst_start=None, stream=None):
+    """Particles per leaf of an FP64 set (any order) into count_out (int64
+    device tensor, one entry per leaf)."""
+    n = x.shape[1]
+    _check_soa(x, tree.dim, n, "float64", "x")
+    _check_vec(count_out, tree.n_leaves, "count_out")
+    _need(count_out.element_size() == 8, "count_out must hold 64-bit integers")
+    _check_inst(tree, inst_start)
+    P = _particles(n, x=x, inst_start=inst_start)
+    check(lib().pic_leaf_counts(tree.handle, C.byref(P), C.c_void_p(_ptr(count_out)), C.c_void_p(_stream(stream))),
+          "pic_leaf_counts")
+
+
+def adapt(tree: Tree, leaf_count, ppc: int, max_level: int):
+    """One ppc-driven adaptation of a single tree (host): returns the new
+    tree's TreeSpec (refine masks), or None when nothing changes."""
+    cnt = np.ascontiguousarray(np.asarray(leaf_count, dtype=np.int64))
+    _need(cnt.shape == (tree.n_leaves,), "leaf_count needs one entry per leaf")
+    ln, nl = C.c_size_t(0), C.c_int32(0)
+    st = lib().pic_tree_adapt(tree.handle, cnt.ctypes.data, int(ppc), int(max_level), None, 0, C.byref(ln),
+                              C.byref(nl))
+    if st not in (_capi.PIC_OK, _capi.PIC_E_CAPACITY):
+        check(st, "pic_tree_adapt")
+    masks = np.zeros(max(ln.value, 1), np.uint8)
+    check(lib().pic_tree_adapt(tree.handle, cnt.ctypes.data, int(ppc), int(max_level), masks.ctypes.data,
+                               masks.size, C.byref(ln), C.byref(nl)), "pic_tree_adapt")
+    L, d = nl.value, tree.dim
+    levels, off = [], 0
+    for lev in range(L):
+        k = 3 ** (d * lev)
+        levels.append(masks[off:off + k].copy())
+        off += k
+    old = tree.specs[0]
+    if old.max_level == L and np.array_equal(np.asarray(old.masks_concat(), np.uint8).ravel(),
+                                             np.concatenate(levels) if levels else np.zeros(0, np.uint8)):
+        return None
+    return RefineMasks(d, L, levels)
+
+
 def rebin(tree: Tree, scheme: int, new_bin, old_start, cols_in: Sequence, cols_out: Sequence, new_start,
           scratch, stats=None, stream=None):
     """Stable re-bin; permutes every column of cols_in into cols_out."""
@@ -419,6 +491,53 @@ class Stepper:
              self.rho, self.scratch, extra_in, extra_out, q_col, q_uniform, inst_start=self.inst_start,
              qmdt_dev=qmdt_dev, dt_dev=dt_dev, stats=stats)
         self._swap()
+
+
+class FreeStreamRun(Stepper):
+    """The particle-handling benchmark of the paper's results section on one
+    tree: free streaming (pic_free_stream), the stable re-bin (pic_rebin),
+    and the ppc-driven adaptation of the tree (pic_leaf_counts,
+    pic_tree_adapt, a new tree, pic_locate and pic_rebin against it)."""
+
+    def __init__(self, tree: Tree, scheme: int, x, v, ids=None, device="cuda"):
+        super().__init__(tree, scheme, x, v, ids=ids, device=device)
+        self.device = device
+
+    def move(self, dt: float, boundary: int = _capi.REFLECTING, flops: int = 0):
+        free_stream(self.tree, self.scheme, self.x, self.v, dt, boundary, flops, self.bin)
+
+    def step_free(self, dt: float, boundary: int = _capi.REFLECTING, flops: int = 0, stats=None):
+        self.move(dt, boundary, flops)
+        self.rebin(stats)
+
+    def leaf_counts(self):
+        """Particles per leaf (host int64 array): the PIT bin offsets, or the
+        counting kernel for PIDT."""
+        import torch
+        if self.scheme == PIT:
+            return np.diff(self.start.cpu().numpy())
+        c = torch.empty(self.tree.n_leaves, dtype=torch.int64, device=self.x.device)
+        leaf_counts(self.tree, self.x, c)
+        return c.cpu().numpy()
+
+    def adapt(self, ppc: int, max_level: int) -> bool:
+        """One adaptation; on a change the particles are re-sorted into the
+        new tree (stable: old order within each new bin).  Returns whether
+        the tree changed."""
+        import torch
+        spec = adapt(self.tree, self.leaf_counts(), ppc, max_level)
+        if spec is None:
+            return False
+        tree = Tree(spec).upload(self.device)
+        nb = tree.n_bins(self.scheme)
+        dev = self.x.device
+        self.tree = tree
+        self.start = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.start2 = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.scratch = torch.empty(scratch_bytes(tree, self.n, self.scheme) // 8 + 1, dtype=torch.int64, device=dev)
+        self.rho = torch.zeros(tree.n_vertices, dtype=torch.float64, device=dev)
+        self.initial_sort()
+        return True
 
 
 class Stepper32:

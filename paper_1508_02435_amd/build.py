@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 SOURCES = ["pic_tree.hip", "pic_kernels.hip", "pic_rebin.hip", "pic_rank.hip", "pic_step.hip", "pic_f32.hip",
-           "pic_stats.hip", "pic_capi.hip", "pic_profile.hip"]
+           "pic_stats.hip", "pic_move.hip", "pic_capi.hip", "pic_profile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

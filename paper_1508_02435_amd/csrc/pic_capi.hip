@@ -506,6 +506,50 @@ pic_status pic_gather_push(const pic_tree *t, int32_t scheme, int32_t precision,
     return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
+pic_status pic_free_stream(const pic_tree *t, int32_t scheme, int32_t precision, pic_particles *p, double dt,
+                           const pic_push_params *params, int32_t boundary, int32_t flops, uint32_t *bin,
+                           void *stream) {
+    if (!t || !valid_scheme(scheme) || precision != PIC_F64 || !particles_ok(t, p, precision, true))
+        return PIC_E_ARG;
+    if (boundary != PIC_PERIODIC && boundary != PIC_REFLECTING) return PIC_E_ARG;
+    if (flops < 0 || flops > (1 << 20) || (flops & 1)) return PIC_E_ARG;
+    if (p->n > 0 && !bin) return PIC_E_ARG;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_free_stream(t, scheme, p, dt, params ? params->dt_dev : nullptr, boundary, flops, bin,
+                              (hipStream_t)stream) == hipSuccess
+               ? PIC_OK
+               : PIC_E_HIP;
+}
+
+pic_status pic_leaf_counts(const pic_tree *t, const pic_particles *p, uint64_t *count, void *stream) {
+    if (!t || !particles_ok(t, p, PIC_F64, false) || !count) return PIC_E_ARG;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_leaf_counts(t, p, (unsigned long long *)count, (hipStream_t)stream) == hipSuccess ? PIC_OK
+                                                                                                 : PIC_E_HIP;
+}
+
+pic_status pic_tree_adapt(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int32_t max_level,
+                          uint8_t *masks, size_t masks_cap, size_t *masks_len, int32_t *new_max_level) {
+    if (!t || t->n_inst != 1 || ppc < 0 || !masks_len || !new_max_level) return PIC_E_ARG;
+    if (max_level < 0 || max_level > PIC_MAX_LEVEL || t->dim * max_level > 36) return PIC_E_ARG;
+    const int64_t nl = (int64_t)t->inst[0].leaf_level.size();
+    if (nl > 0 && !leaf_count) return PIC_E_ARG;
+    for (int64_t r = 0; r < nl; ++r)
+        if (leaf_count[r] < 0) return PIC_E_ARG;
+    std::vector<uint8_t> m;
+    int L = 0;
+    pic_status st = adapt_masks(t, leaf_count, ppc, max_level, m, L);
+    if (st != PIC_OK) return st;
+    *masks_len = m.size();
+    *new_max_level = L;
+    if (masks_cap < m.size()) return PIC_E_CAPACITY;
+    if (!m.empty()) {
+        if (!masks) return PIC_E_ARG;
+        std::copy(m.begin(), m.end(), masks);
+    }
+    return PIC_OK;
+}
+
 size_t pic_scratch_bytes(const pic_tree *t, int64_t n, int32_t scheme, int32_t precision) {
     if (!t || !valid_scheme(scheme) || n < 0 || !valid_precision(t, precision)) return 0;
     if (precision == PIC_F32_OFFSET) return step_f32_scratch_bytes(t, n, scheme);

@@ -153,6 +153,12 @@ hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, con
                            const Cols &extra, pic_particles *out, int64_t *new_start, int q_col, double q_uniform,
                            double *rho, void *scratch, size_t scratch_bytes, void *stats, hipStream_t s);
 hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *const *v, double dt, hipStream_t s);
+// The particle-handling benchmark (pic_move.hip).
+hipError_t launch_free_stream(const pic_tree *t, int scheme, pic_particles *p, double dt, const double *dt_dev,
+                              int boundary, int flops, uint32_t *bin, hipStream_t s);
+hipError_t launch_leaf_counts(const pic_tree *t, const pic_particles *p, unsigned long long *count, hipStream_t s);
+pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int max_level,
+                       std::vector<uint8_t> &masks, int &new_L);
 // Re-bin statistics of a sorted set (old_start) whose new bins are bins[p] >> shift
 // (pic_stats.hip); adds to the caller's pic_rebin_stats record.
 hipError_t launch_rebin_stats(const pic_tree *t, int scheme, const int64_t *old_start, const uint32_t *bins,

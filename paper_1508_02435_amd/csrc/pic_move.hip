@@ -1,0 +1,279 @@
+// pic_move.hip -- the particle-handling benchmark of the paper's results
+// section (Sec. 6 setup): free streaming with periodic or reflecting walls
+// and artificial flops per move, particle counts per leaf, and the
+// ppc-driven refinement and coarsening of a tree (host side).
+#include <hip/hip_runtime.h>
+
+#include <unordered_map>
+#include <vector>
+
+#include "pic_launch.h"
+
+namespace pic {
+
+// One axis of a free-streaming move: x + v dt, then the wall rule.  Periodic:
+// x - floor(x), 1 -> 0 (the push's wrap).  Reflecting: mirrored at 0 (x ->
+// -x) or at 1 (x -> 2 - x, exact for x in [1, 2)), with the velocity
+// component negated; a landing exactly on 1 goes to the largest double below
+// 1.  A move that one mirror cannot bring back into the box is flagged and
+// clamped (the bin stays in range).
+template <int BC>
+__device__ __forceinline__ void stream_axis(double &x, double &v, double dt, uint32_t &bad) {
+    double y = __dadd_rn(x, __dmul_rn(v, dt));
+    if (BC == PIC_PERIODIC) {
+        y = __dsub_rn(y, floor(y));
+        if (y == 1.0) y = 0.0;
+    } else if (y < 0.0) {
+        y = -y;
+        v = -v;
+    } else if (y >= 1.0) {
+        y = __dsub_rn(2.0, y);
+        v = -v;
+        if (y == 1.0) y = 0x1.fffffffffffffp-1;
+    }
+    if (!(y >= 0.0 && y < 1.0)) {
+        bad |= (y - y == 0.0) ? PIC_DEV_RANGE : PIC_DEV_NONFINITE;
+        y = (y >= 1.0) ? 0x1.fffffffffffffp-1 : 0.0;
+    }
+    x = y;
+}
+
+template <int D, int SCHEME, bool REG, bool MULTI, int BC>
+__global__ __launch_bounds__(256) void k_free_stream(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double dt0,
+                                                     const double *dt_arr, const int64_t *inst_start, int flops,
+                                                     uint32_t *bin_out) {
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        int ii = 0;
+        if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
+        const DevInst &in = MULTI ? t.inst[ii] : in0;
+        const double dt = (MULTI && dt_arr) ? dt_arr[ii] : dt0;
+        uint32_t bad = 0;
+        double xv[D], vv[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xv[k] = P.x[k][p];
+            vv[k] = P.v[k][p];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) stream_axis<BC>(xv[k], vv[k], dt, bad);
+        // the artificial flops: a dependent chain of multiplies and adds
+        // whose result only feeds a test that never holds
+        double a = xv[0];
+        for (int f = 0; f < flops / 2; ++f) a = __dadd_rn(__dmul_rn(a, 0.5), 0.25);
+        if (a < -1.0) bad |= PIC_DEV_RANGE;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            P.x[k][p] = xv[k];
+            P.v[k][p] = vv[k];
+        }
+        Axis ax[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
+        bin_out[p] = bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
+        if (bad) flag_status(t.status, bad);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *a, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0ull;
+}
+
+// Particles per leaf (forest-wide leaf ranks): integer adds, so the counts
+// do not depend on the order of the atomics.
+template <int D, bool REG, bool MULTI>
+__global__ __launch_bounds__(256) void k_leaf_counts(DevTree t, DevInst in0, F64Ptrs P, int64_t n,
+                                                     const int64_t *inst_start, unsigned long long *count) {
+    __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
+    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const DevInst &in = MULTI ? t.inst[inst_of(inst_start, t.n_inst, p)] : in0;
+        uint32_t bad = 0;
+        Axis ax[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) ax[k] = scale_axis(P.x[k][p], in.Sd, in.S, bad);
+        atomicAdd(&count[bin_of<D, PIC_PIT, REG>(t, in, ax, lds, lds_n)], 1ull);
+        if (bad) flag_status(t.status, bad);
+    }
+}
+
+#define PIC_FS(D, SCH, REG, MULTI)                                                                             \
+    do {                                                                                                       \
+        if (boundary == PIC_PERIODIC)                                                                          \
+            PIC_LAUNCH("free_stream", (k_free_stream<D, SCH, REG, MULTI, PIC_PERIODIC>), dim3(grid), dim3(256), 0, \
+                       s, t->dt, t->inst0, P, p->n, dt, da, p->inst_start_dev, flops, bin);                    \
+        else                                                                                                   \
+            PIC_LAUNCH("free_stream", (k_free_stream<D, SCH, REG, MULTI, PIC_REFLECTING>), dim3(grid), dim3(256), \
+                       0, s, t->dt, t->inst0, P, p->n, dt, da, p->inst_start_dev, flops, bin);                 \
+    } while (0)
+#define PIC_FS_RM(D, SCH)                                                                                      \
+    do {                                                                                                       \
+        if (multi) { if (reg) PIC_FS(D, SCH, true, true); else PIC_FS(D, SCH, false, true); }                  \
+        else { if (reg) PIC_FS(D, SCH, true, false); else PIC_FS(D, SCH, false, false); }                      \
+    } while (0)
+
+hipError_t launch_free_stream(const pic_tree *t, int scheme, pic_particles *p, double dt, const double *da,
+                              int boundary, int flops, uint32_t *bin, hipStream_t s) {
+    if (p->n == 0) return hipSuccess;
+    F64Ptrs P = make_ptrs(t, p, nullptr, nullptr);
+    const int grid = grid_for(p->n, 256, 1 << 20);
+    const bool multi = t->n_inst > 1;
+    const bool reg = t->reg_kernels != 0;
+    if (t->dim == 2) {
+        if (scheme == PIC_PIT) PIC_FS_RM(2, 0); else PIC_FS_RM(2, 1);
+    } else {
+        if (scheme == PIC_PIT) PIC_FS_RM(3, 0); else PIC_FS_RM(3, 1);
+    }
+    return hipGetLastError();
+}
+#undef PIC_FS_RM
+#undef PIC_FS
+
+hipError_t launch_leaf_counts(const pic_tree *t, const pic_particles *p, unsigned long long *count,
+                              hipStream_t s) {
+    const int64_t nl = t->leaf_off.back();
+    PIC_LAUNCH("fill", k_fill_u64, dim3(grid_for(nl, 256, 1 << 16)), dim3(256), 0, s, count, nl);
+    if (p->n == 0) return hipGetLastError();
+    F64Ptrs P = make_ptrs(t, p, nullptr, nullptr);
+    const int grid = grid_for(p->n, 256, 1 << 20);
+    const bool multi = t->n_inst > 1, reg = t->reg_kernels != 0;
+#define PIC_LC(D, REG, MULTI)                                                                                  \
+    PIC_LAUNCH("leaf_counts", (k_leaf_counts<D, REG, MULTI>), dim3(grid), dim3(256), 0, s, t->dt, t->inst0, P, \
+               p->n, p->inst_start_dev, count)
+    if (t->dim == 2) {
+        if (multi) { if (reg) PIC_LC(2, true, true); else PIC_LC(2, false, true); }
+        else { if (reg) PIC_LC(2, true, false); else PIC_LC(2, false, false); }
+    } else {
+        if (multi) { if (reg) PIC_LC(3, true, true); else PIC_LC(3, false, true); }
+        else { if (reg) PIC_LC(3, true, false); else PIC_LC(3, false, false); }
+    }
+#undef PIC_LC
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ ppc-driven adaptation
+//
+// Per level a dense state byte for every cell position (the layout of the
+// refine masks): 0 absent, 1 leaf, 2 refined, 3 leaf to refine, 4 refined
+// cell to coarsen.  Leaves come from the tree's leaf table (level and
+// coordinates per Peano rank); every ancestor of a leaf is refined.
+namespace {
+
+int64_t lex_of(int dim, int64_t n, const int64_t *a) {
+    int64_t r = 0, m = 1;
+    for (int k = 0; k < dim; ++k) {
+        r += a[k] * m;
+        m *= n;
+    }
+    return r;
+}
+
+}  // namespace
+
+pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int max_level,
+                       std::vector<uint8_t> &masks, int &new_L) {
+    const pic::HostInst &h = t->inst[0];
+    const int d = t->dim, L = h.L;
+    const int top = std::max(L, std::min(L + 1, max_level));   // deepest level the new tree can reach
+    std::vector<std::vector<uint8_t>> st(top + 1);
+    for (int l = 0; l <= top; ++l) st[l].assign((size_t)pow3_u64(d * l), 0);
+    std::unordered_map<int64_t, int64_t> cnt;   // (level, lex) -> particles, leaves only
+    const int64_t nl = (int64_t)h.leaf_level.size();
+    for (int64_t r = 0; r < nl; ++r) {
+        const int l = h.leaf_level[r];
+        int64_t a[3];
+        for (int k = 0; k < d; ++k) a[k] = h.leaf_coord[(size_t)r * d + k];
+        const int64_t id = lex_of(d, pow3_u64(l), a);
+        st[l][id] = 1;
+        cnt[id * 32 + l] = leaf_count[r];
+        for (int up = l - 1; up >= 0; --up) {
+            for (int k = 0; k < d; ++k) a[k] /= 3;
+            uint8_t &s = st[up][lex_of(d, pow3_u64(up), a)];
+            if (s == 2) break;
+            s = 2;
+        }
+    }
+    auto count_of = [&](int l, int64_t id) -> int64_t {
+        auto it = cnt.find(id * 32 + l);
+        return it == cnt.end() ? 0 : it->second;
+    };
+    // refine: overfull leaves above the level cap
+    for (int l = 0; l <= L && l < max_level; ++l)
+        for (size_t i = 0; i < st[l].size(); ++i)
+            if (st[l][i] == 1 && count_of(l, (int64_t)i) > ppc) st[l][i] = 3;
+    // coarsen: refined non-root cells whose children are all leaves (none of
+    // them being refined) holding together at most ppc particles
+    for (int l = 1; l < L; ++l) {
+        const int64_t n = pow3_u64(l);
+        for (size_t i = 0; i < st[l].size(); ++i) {
+            if (st[l][i] != 2) continue;
+            int64_t a[3], r = (int64_t)i;
+            for (int k = 0; k < d; ++k) {
+                a[k] = r % n;
+                r /= n;
+            }
+            bool leaves = true;
+            int64_t sum = 0;
+            const int nkid = (int)pow3_u64(d);
+            for (int c = 0; c < nkid && leaves; ++c) {
+                int64_t b[3], cc = c;
+                for (int k = 0; k < d; ++k) {
+                    b[k] = 3 * a[k] + cc % 3;
+                    cc /= 3;
+                }
+                const int64_t id = lex_of(d, 3 * n, b);
+                if (st[l + 1][id] != 1) leaves = false;
+                else sum += count_of(l + 1, id);
+            }
+            if (leaves && sum <= ppc) st[l][i] = 4;
+        }
+    }
+    // the new masks: a cell is refined iff it is reached through refined
+    // cells and is refined (2) or to be refined (3)
+    std::vector<std::vector<uint8_t>> ref(top + 1);
+    ref[0].assign(1, 0);
+    std::vector<uint8_t> live(1, 1);
+    new_L = 0;
+    for (int l = 0; l <= top; ++l) {
+        const int64_t n = pow3_u64(l);
+        std::vector<uint8_t> m(st[l].size(), 0);
+        bool any = false;
+        for (size_t i = 0; i < m.size(); ++i)
+            if (live[i] && (st[l][i] == 2 || st[l][i] == 3)) {
+                m[i] = 1;
+                any = true;
+            }
+        if (!any) break;
+        ref[l] = m;
+        new_L = l + 1;
+        if (l + 1 > top) break;
+        std::vector<uint8_t> nxt((size_t)pow3_u64(d * (l + 1)), 0);
+        for (size_t i = 0; i < m.size(); ++i) {
+            if (!m[i]) continue;
+            int64_t a[3], r = (int64_t)i;
+            for (int k = 0; k < d; ++k) {
+                a[k] = r % n;
+                r /= n;
+            }
+            const int nkid = (int)pow3_u64(d);
+            for (int c = 0; c < nkid; ++c) {
+                int64_t b[3], cc = c;
+                for (int k = 0; k < d; ++k) {
+                    b[k] = 3 * a[k] + cc % 3;
+                    cc /= 3;
+                }
+                nxt[lex_of(d, 3 * n, b)] = 1;
+            }
+        }
+        live.swap(nxt);
+    }
+    masks.clear();
+    for (int l = 0; l < new_L; ++l) masks.insert(masks.end(), ref[l].begin(), ref[l].end());
+    return PIC_OK;
+}
+
+}  // namespace pic

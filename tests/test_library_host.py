@@ -221,3 +221,62 @@ def test_tables_off_gives_no_fp32_form():
         pic.tune("regular_tables", before)
     assert pic.scratch_bytes(t, 1000, pic.PIT, pic.F32_OFFSET) == 0
     assert pic.scratch_bytes(t, 1000, pic.PIT) > 0
+
+
+def _adapt_cases():
+    rng = np.random.default_rng(21)
+    out = []
+    for spec, start, n, ppc, cap in [(W.regular_tree(2, 1), 1.0, 2000, 50, 5), (W.regular_tree(2, 2), 0.1, 3000, 30, 5),
+                                     (W.disc_tree(2, 1, 3), 1.0, 1500, 8, 4), (W.regular_tree(3, 1), 0.1, 1200, 20, 3),
+                                     (W.disc_tree(3, 1, 2), 1.0, 800, 4, 3), (W.regular_tree(2, 3), 0.3, 400, 6, 3),
+                                     (W.regular_tree(2, 0), 1.0, 50, 10, 2)]:
+        out.append((spec, rng.random((spec.dim, n)) * start, ppc, cap))
+    return out
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_tree_adapt_equals_oracle_rule(case):
+    """pic_tree_adapt (host code of the library) against the oracle's rule,
+    applied repeatedly until the tree stops changing: the masks agree byte
+    for byte at every application."""
+    spec, x, ppc, cap = _adapt_cases()[case]
+    for _ in range(8):
+        o = oracle.OracleTree(spec)
+        t = pic.Tree(spec)
+        counts = np.bincount(o.bin_of(x, oracle.PIT), minlength=o.n_leaves)
+        got = pic.adapt(t, counts, ppc, cap)
+        want = oracle.adapt(spec, x, ppc, cap)
+        same = want.max_level == spec.max_level and np.array_equal(want.masks_concat(), spec.masks_concat())
+        if same:
+            assert got is None
+            break
+        assert got is not None and got.max_level == want.max_level
+        assert np.array_equal(got.masks_concat(), want.masks_concat())
+        spec = want
+
+
+def test_tree_adapt_rejects_bad_arguments():
+    t = pic.Tree(W.regular_tree(2, 1))
+    cnt = np.zeros(9, np.int64)
+    ln, nl = C.c_size_t(0), C.c_int32(0)
+    L = _capi.lib()
+    assert L.pic_tree_adapt(t.handle, cnt.ctypes.data, -1, 3, None, 0, C.byref(ln), C.byref(nl)) == _capi.PIC_E_ARG
+    assert L.pic_tree_adapt(t.handle, cnt.ctypes.data, 5, 19, None, 0, C.byref(ln), C.byref(nl)) == _capi.PIC_E_ARG
+    bad = cnt.copy()
+    bad[3] = -2
+    assert L.pic_tree_adapt(t.handle, bad.ctypes.data, 5, 3, None, 0, C.byref(ln), C.byref(nl)) == _capi.PIC_E_ARG
+    cnt[4] = 10
+    assert L.pic_tree_adapt(t.handle, cnt.ctypes.data, 5, 3, None, 0, C.byref(ln), C.byref(nl)) == _capi.PIC_E_CAPACITY
+    assert (ln.value, nl.value) == (1 + 9, 2)
+    forest = pic.Tree([W.regular_tree(2, 1), W.regular_tree(2, 1)])
+    cnt2 = np.zeros(18, np.int64)
+    assert L.pic_tree_adapt(forest.handle, cnt2.ctypes.data, 5, 3, None, 0, C.byref(ln), C.byref(nl)) == _capi.PIC_E_ARG
+
+
+def test_free_stream_rejects_bad_arguments():
+    t = pic.Tree(W.regular_tree(2, 1))
+    L = _capi.lib()
+    P = _capi.Particles()
+    for boundary, flops in ((2, 0), (-1, 0), (1, 3), (1, -2), (0, (1 << 20) + 2)):
+        assert L.pic_free_stream(t.handle, 0, 0, C.byref(P), 0.1, None, boundary, flops, None, None) == _capi.PIC_E_ARG
+    assert L.pic_free_stream(t.handle, 0, 1, C.byref(P), 0.1, None, 1, 0, None, None) == _capi.PIC_E_ARG
