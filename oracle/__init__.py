@@ -287,6 +287,47 @@ def step(tree: OracleTree, x, v, E, qmdt, dt, bin_start, scheme=PIT, q=None, q_u
 # ---------------------------------------------------------------------------
 # Support outside the hot path (regular periodic trees only): Poisson + field
 # ---------------------------------------------------------------------------
+# raPIDT's analysed attribute (paper Sec. 5.4, Eq. (vmax))
+# ---------------------------------------------------------------------------
+
+def vmax_cells(spec, x, v, scheme, dt=None):
+    """The per-cell maximum velocity component of raPIDT, from its
+    definition: for a leaf, the largest |v_k| over the particles it holds
+    (PIT) or over the particles of the 2^d dual cells of its corners at its
+    level (PIDT); for a refined cell, the largest value of its children,
+    i.e. of every leaf below it.  Returned as one float64 array per level in
+    the layout of the refine masks (lexicographic, 0 for cells that do not
+    exist); with ``dt`` also the predicate v_max(c) dt <= h(c) per cell
+    (uint8, 0 for cells that do not exist)."""
+    d, L = spec.dim, spec.max_level
+    t = OracleTree(spec)
+    speed = np.max(np.abs(np.asarray(v, np.float64)), axis=0) if np.asarray(v).size else np.zeros(0)
+    leaf, pidt, _ = t.locate(x) if speed.size else (np.zeros(0, np.int32),) * 3
+    lv = t.leaves()
+    per_leaf = np.zeros(t.n_leaves)
+    if scheme == PIT:
+        np.maximum.at(per_leaf, leaf, speed)
+    else:
+        per_bin = np.zeros(t.n_pidt)
+        np.maximum.at(per_bin, pidt, speed)
+        per_leaf = per_bin[lv["pidt"]].max(axis=1)
+    out = [np.zeros((3 ** l) ** d) for l in range(L + 1)]
+    exists = [np.zeros((3 ** l) ** d, bool) for l in range(L + 1)]
+    for r in range(t.n_leaves):
+        l, a = int(lv["level"][r]), [int(c) for c in lv["coord"][r]]
+        for up in range(l, -1, -1):          # the leaf and every ancestor
+            n = 3 ** up
+            i = sum(a[k] * n ** k for k in range(d))
+            out[up][i] = max(out[up][i], per_leaf[r])
+            exists[up][i] = True
+            a = [c // 3 for c in a]
+    if dt is None:
+        return out
+    quiet = [(exists[l] & (out[l] * dt <= 3.0 ** -l)).astype(np.uint8) for l in range(L + 1)]
+    return out, quiet
+
+
+# ---------------------------------------------------------------------------
 # ppc-driven dynamic adaptivity (paper Sec. 6 setup; Sec. 5 opening remark)
 # ---------------------------------------------------------------------------
 

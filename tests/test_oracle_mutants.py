@@ -154,3 +154,37 @@ def test_pins_catch_adapt_mutant(name):
             caught = True
             break
     assert caught, f"no pin catches mutant {name}"
+
+
+VMAX_MUTANTS = {
+    "pidt_from_own_leaf_only": ("per_leaf = per_bin[lv[\"pidt\"]].max(axis=1)", "np.maximum.at(per_leaf, leaf, speed)"),
+    "leaves_only_no_ancestors": ("for up in range(l, -1, -1):", "for up in range(l, l - 1, -1):"),
+    "predicate_strict": ("out[l] * dt <= 3.0 ** -l", "out[l] * dt < 3.0 ** -l * 0.5"),
+    "speed_from_axis0": ("speed = np.max(np.abs(np.asarray(v, np.float64)), axis=0)",
+                         "speed = np.abs(np.asarray(v, np.float64))[0]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(VMAX_MUTANTS))
+def test_pins_catch_vmax_mutant(name):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.vmax_cells))
+    old, new = VMAX_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), ns)
+    saved = oracle.vmax_cells
+    oracle.vmax_cells = ns["vmax_cells"]
+    caught = False
+    try:
+        for pin in (PW.test_vmax_hand_case, lambda: PW.test_vmax_of_a_cell_is_the_max_over_its_subtree_particles(0),
+                    lambda: PW.test_vmax_of_a_cell_is_the_max_over_its_subtree_particles(1)):
+            try:
+                pin()
+            except (AssertionError, ValueError):
+                caught = True
+                break
+    finally:
+        oracle.vmax_cells = saved
+    assert caught, f"no pin catches mutant {name}"

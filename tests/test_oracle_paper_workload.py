@@ -183,3 +183,55 @@ def test_repeated_adaptation_reaches_the_ppc_fixed_point(dim, start, adapt=None)
             assert sum(cnt[sb] for sb in sib) > ppc
     if start == "subbox":
         assert spec.max_level > 1
+
+
+# ---------------------------------------------------------------------------
+# raPIDT's v_max (Sec. 5.4, Eq. (vmax))
+# ---------------------------------------------------------------------------
+
+def test_vmax_hand_case():
+    spec = W.regular_tree(2, 2)
+    # one particle with |v| = (0.25, -0.7) in finest cell (4, 4), one slow in
+    # cell (0, 0); everything else empty
+    x = np.array([[4.5 / 9, 0.5 / 9], [4.5 / 9, 0.5 / 9]])
+    v = np.array([[0.25, 0.01], [-0.7, 0.0]])
+    pit, q = oracle.vmax_cells(spec, x, v, oracle.PIT, dt=0.5)
+    assert pit[0][0] == 0.7
+    assert pit[1][1 + 3 * 1] == 0.7 and pit[1][0] == 0.01 and pit[1].sum() == 0.71
+    assert pit[2][4 + 9 * 4] == 0.7 and pit[2][0] == 0.01 and np.count_nonzero(pit[2]) == 2
+    # predicate: 0.7 * 0.5 <= 1/3 fails at level 1, holds at level 0
+    assert q[0][0] == 1 and q[1][4] == 0 and q[1][0] == 1 and q[2][40] == 0
+    # dt = 0.3: 0.21 <= h = 1/3 at level 1 (though above h/2), above 1/9 at level 2
+    _, q3 = oracle.vmax_cells(spec, x, v, oracle.PIT, dt=0.3)
+    assert q3[1][4] == 1 and q3[2][40] == 0
+    # cells that do not exist are never quiet
+    _, qa = oracle.vmax_cells(W.disc_tree(2, 1, 2), x, v, oracle.PIT, dt=0.3)
+    assert qa[2].sum() == np.count_nonzero(W.disc_tree(2, 1, 2).refine[1]) * 9 - (1 if qa[2][40] == 0 else 0)
+    # PIDT: the fast particle's dual cell is that of vertex (5, 5) (nearest
+    # corner of cell (4, 4), ties up), shared by the four leaves around it
+    pidt = oracle.vmax_cells(spec, x, v, oracle.PIDT)
+    for c in [(4, 4), (5, 4), (4, 5), (5, 5)]:
+        assert pidt[2][c[0] + 9 * c[1]] == 0.7
+    assert pidt[2][3 + 9 * 3] == 0.0
+
+
+@pytest.mark.parametrize("scheme", [oracle.PIT, oracle.PIDT])
+def test_vmax_of_a_cell_is_the_max_over_its_subtree_particles(scheme):
+    rng = np.random.default_rng(8)
+    spec = W.disc_tree(2, 1, 3)
+    x, v = rng.random((2, 700)), rng.uniform(-1, 1, (2, 700))
+    out = oracle.vmax_cells(spec, x, v, scheme)
+    S = 27
+    I = np.minimum(np.floor(x * S), S - 1).astype(np.int64)
+    sp = np.abs(v).max(axis=0)
+    # the root holds every particle; for PIT a level-1 cell holds exactly
+    # the particles inside it, for PIDT at least those
+    assert out[0][0] == sp.max()
+    for a0 in range(3):
+        for a1 in range(3):
+            inside = (I[0] // 9 == a0) & (I[1] // 9 == a1)
+            val = out[1][a0 + 3 * a1]
+            if scheme == oracle.PIT:
+                assert val == (sp[inside].max() if inside.any() else 0.0)
+            else:
+                assert val >= (sp[inside].max() if inside.any() else 0.0)
