@@ -452,6 +452,17 @@ def run_paper(args, scheme):
         lib.pic_stream_push(dim, n, xs, vs, args.dt, sp)
     torch.cuda.synchronize()
     stream_s = (time.perf_counter() - s0) / steps
+    # raPIDT's predicate on the final state: cells whose particles cannot
+    # move by the cell's width in one step (Sec. 5.4)
+    vm, quiet = run.vmax(args.dt)
+    quiet = quiet.cpu().numpy().astype(bool)
+    spec = run.tree.specs[0]
+    refined = np.concatenate([np.asarray(m, np.uint8).ravel() for m in spec.refine] +
+                             [np.zeros(3 ** (dim * spec.max_level), np.uint8)]).astype(bool)
+    n_leaf = int(run.tree.n_leaves)
+    rapidt = {"root_quiet": bool(quiet[0]), "vmax_root": float(vm[0]),
+              "quiet_refined_cells": int((quiet & refined).sum()), "refined_cells": int(refined.sum()),
+              "quiet_leaves": int((quiet & ~refined).sum()), "leaves": n_leaf}
     tot = acc["particles"]
     out = {
         "metric": "particle updates/s (free streaming + re-bin: the paper's particle-handling benchmark)",
@@ -472,6 +483,7 @@ def run_paper(args, scheme):
         "kernels_ms": {k: round(t_ / a_, 4) for k, (a_, t_) in sorted(kt.items(), key=lambda kv: -kv[1][1])},
         "stream_benchmark": {"updates_per_s": n / stream_s, "GBps": 4 * 8 * dim * n / stream_s / 1e9},
         "hot_path_vs_stream": round((n / stream_s) / value, 3),
+        "rapidt": rapidt,
     }
     print(json.dumps(out), flush=True)
 

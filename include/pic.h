@@ -506,6 +506,26 @@ pic_status pic_leaf_counts(const pic_tree *tree, const pic_particles *p, uint64_
 pic_status pic_tree_adapt(const pic_tree *tree, const int64_t *leaf_count, int64_t ppc, int32_t max_level,
                           uint8_t *masks, size_t masks_cap, size_t *masks_len, int32_t *new_max_level);
 
+/*
+ * raPIDT's analysed tree attribute (paper Sec. 5.4, Eq. (vmax)) of a single
+ * tree for a set sorted into `scheme` bins (bin_start_dev):
+ *   leaf c:    v_max(c) = the largest |v_k| over the particles of c (PIT) or
+ *              of the dual cells of c's 2^d corners at c's level (PIDT);
+ *   refined c: v_max(c) = the largest v_max of its children.
+ * vmax_dev (device) receives one double per cell position of levels 0..L in
+ * the layout of the refine masks, level after level ((3^l)^d positions,
+ * lexicographic): (3^(d(L+1)) - 1) / (3^d - 1) entries, 0 where no cell
+ * exists.  quiet_dev (device, nullable, same count of uint8) receives the
+ * paper's predicate v_max(c) * dt <= h(c) = 1/3^l per existing cell (1:
+ * no particle of c can move by a cell width of c in one step), 0 where no
+ * cell exists.  The maxima are exact and do not depend on launch order.
+ * scratch: n_bins doubles (pic_scratch_bytes covers it).  PIC_E_ARG for
+ * forests.
+ */
+pic_status pic_vmax(const pic_tree *tree, int32_t scheme, const pic_particles *p, const int64_t *bin_start_dev,
+                    double dt, double *vmax_dev, uint8_t *quiet_dev, void *scratch, size_t scratch_bytes,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -323,7 +323,7 @@ def vmax_cells(spec, x, v, scheme, dt=None):
             a = [c // 3 for c in a]
     if dt is None:
         return out
-    quiet = [(exists[l] & (out[l] * dt <= 3.0 ** -l)).astype(np.uint8) for l in range(L + 1)]
+    quiet = [(exists[l] & (out[l] * dt <= 1.0 / 3 ** l)).astype(np.uint8) for l in range(L + 1)]
     return out, quiet
 
 

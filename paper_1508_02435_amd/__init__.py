@@ -291,6 +291,26 @@ def leaf_counts(tree: Tree, x, count_out, inst_start=None, stream=None):
           "pic_leaf_counts")
 
 
+def vmax(tree: Tree, scheme: int, x, v, bin_start, dt: float, scratch, stream=None):
+    """raPIDT's per-cell v_max and the predicate v_max dt <= h of a sorted
+    single-tree set: returns two device tensors (float64, uint8), one entry
+    per cell position of levels 0..L in the refine-mask layout."""
+    import torch
+    n = x.shape[1]
+    _check_soa(x, tree.dim, n, "float64", "x")
+    _check_soa(v, tree.dim, n, "float64", "v")
+    _check_vec(bin_start, tree.n_bins(scheme) + 1, "bin_start")
+    L, d = tree.specs[0].max_level, tree.dim
+    cells = (3 ** (d * (L + 1)) - 1) // (3 ** d - 1)
+    out = torch.empty(cells, dtype=torch.float64, device=x.device)
+    quiet = torch.empty(cells, dtype=torch.uint8, device=x.device)
+    P = _particles(n, x=x, v=v)
+    check(lib().pic_vmax(tree.handle, scheme, C.byref(P), C.c_void_p(_ptr(bin_start)), float(dt),
+                         C.c_void_p(_ptr(out)), C.c_void_p(_ptr(quiet)), C.c_void_p(_ptr(scratch)),
+                         scratch.numel() * scratch.element_size(), C.c_void_p(_stream(stream))), "pic_vmax")
+    return out, quiet
+
+
 def adapt(tree: Tree, leaf_count, ppc: int, max_level: int):
     """One ppc-driven adaptation of a single tree (host): returns the new
     tree's TreeSpec (refine masks), or None when nothing changes."""
@@ -519,6 +539,10 @@ class FreeStreamRun(Stepper):
         c = torch.empty(self.tree.n_leaves, dtype=torch.int64, device=self.x.device)
         leaf_counts(self.tree, self.x, c)
         return c.cpu().numpy()
+
+    def vmax(self, dt: float):
+        """raPIDT's per-cell v_max and predicate for this set (see vmax)."""
+        return vmax(self.tree, self.scheme, self.x, self.v, self.start, dt, self.scratch)
 
     def adapt(self, ppc: int, max_level: int) -> bool:
         """One adaptation; on a change the particles are re-sorted into the

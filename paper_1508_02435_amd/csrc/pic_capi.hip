@@ -528,6 +528,18 @@ pic_status pic_leaf_counts(const pic_tree *t, const pic_particles *p, uint64_t *
                                                                                                  : PIC_E_HIP;
 }
 
+pic_status pic_vmax(const pic_tree *t, int32_t scheme, const pic_particles *p, const int64_t *bin_start, double dt,
+                    double *vmax, uint8_t *quiet, void *scratch, size_t scratch_bytes, void *stream) {
+    if (!t || t->n_inst != 1 || !valid_scheme(scheme) || !particles_ok(t, p, PIC_F64, true) || !vmax ||
+        !bin_start || !scratch)
+        return PIC_E_ARG;
+    if (scratch_bytes < vmax_scratch_bytes(t, scheme)) return PIC_E_SCRATCH;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_vmax(t, scheme, p, bin_start, dt, vmax, quiet, scratch, (hipStream_t)stream) == hipSuccess
+               ? PIC_OK
+               : PIC_E_HIP;
+}
+
 pic_status pic_tree_adapt(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int32_t max_level,
                           uint8_t *masks, size_t masks_cap, size_t *masks_len, int32_t *new_max_level) {
     if (!t || t->n_inst != 1 || ppc < 0 || !masks_len || !new_max_level) return PIC_E_ARG;

@@ -159,6 +159,10 @@ hipError_t launch_free_stream(const pic_tree *t, int scheme, pic_particles *p, d
 hipError_t launch_leaf_counts(const pic_tree *t, const pic_particles *p, unsigned long long *count, hipStream_t s);
 pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int max_level,
                        std::vector<uint8_t> &masks, int &new_L);
+hipError_t launch_vmax(const pic_tree *t, int scheme, const pic_particles *p, const int64_t *bin_start, double dt,
+                       double *cells, uint8_t *quiet, void *scratch, hipStream_t s);
+size_t vmax_scratch_bytes(const pic_tree *t, int scheme);
+int64_t vmax_cells(const pic_tree *t);
 // Re-bin statistics of a sorted set (old_start) whose new bins are bins[p] >> shift
 // (pic_stats.hip); adds to the caller's pic_rebin_stats record.
 hipError_t launch_rebin_stats(const pic_tree *t, int scheme, const int64_t *old_start, const uint32_t *bins,

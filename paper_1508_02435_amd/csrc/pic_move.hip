@@ -155,6 +155,122 @@ hipError_t launch_leaf_counts(const pic_tree *t, const pic_particles *p, unsigne
     return hipGetLastError();
 }
 
+// ------------------------------------------------- raPIDT's v_max attribute
+//
+// Cells are addressed as in the refine masks, levels 0..L back to back,
+// (3^l)^d positions per level, lexicographic.  A wavefront per bin takes the
+// largest velocity component of the bin's particles; a thread per leaf then
+// takes its value (its own bin for PIT, the largest of its corners' dual
+// cells for PIDT) up its ancestor chain with atomicMax on the bit patterns
+// (non-negative doubles order like their bits, and max does not depend on
+// the order of the updates).
+
+// First cell of level l: sum of (3^j)^d for j < l = (3^(dl) - 1) / (3^d - 1).
+__host__ __device__ inline int64_t cell_off(int d, int l) {
+    int64_t a = 1, b = 1;
+    for (int j = 0; j < d * l; ++j) a *= 3;
+    for (int j = 0; j < d; ++j) b *= 3;
+    return (a - 1) / (b - 1);
+}
+
+__global__ __launch_bounds__(256) void k_vmax_bins(const F64Ptrs P, int dim, const int64_t *bin_start, int64_t n_bins,
+                                                   double *bval) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t b = wid; b < n_bins; b += nw) {
+        const int64_t p0 = bin_start[b], p1 = bin_start[b + 1];
+        double m = 0.0;
+        for (int64_t p = p0 + lane; p < p1; p += 64)
+            for (int k = 0; k < dim; ++k) m = fmax(m, fabs(P.v[k][p]));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) bval[b] = m;
+    }
+}
+
+__global__ void k_fill_cells(unsigned long long *v, uint8_t *mark, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        v[i] = 0ull;
+        if (mark) mark[i] = 0;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_vmax_leaves(DevTree t, int scheme, const double *bval, int64_t n_leaves,
+                                                     unsigned long long *cells, uint8_t *mark) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_leaves; r += stride) {
+        double val = 0.0;
+        if (scheme == PIC_PIT) {
+            val = bval[r];
+        } else {
+            for (int c = 0; c < (1 << D); ++c) val = fmax(val, bval[t.leaf_pidt[r * (1 << D) + c]]);
+        }
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(val);
+        int64_t a[D];
+        for (int k = 0; k < D; ++k) a[k] = t.leaf_coord[r * D + k];
+        for (int l = t.leaf_level[r]; l >= 0; --l) {
+            int64_t n = 1, idx = 0;
+            for (int j = 0; j < l; ++j) n *= 3;
+            int64_t m = 1;
+            for (int k = 0; k < D; ++k) {
+                idx += a[k] * m;
+                m *= n;
+            }
+            const int64_t c = cell_off(D, l) + idx;
+            atomicMax(&cells[c], bits);
+            if (mark) mark[c] = 1;
+            for (int k = 0; k < D; ++k) a[k] /= 3;
+        }
+    }
+}
+
+// The predicate v_max(c) dt <= h(c), h = 1 / 3^l (one rounding), for the
+// cells the leaves marked as existing.
+__global__ void k_vmax_quiet(const double *cells, int d, int L, double dt, uint8_t *mark) {
+    const int64_t n = cell_off(d, L + 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!mark[i]) continue;
+        int l = 0;
+        while (cell_off(d, l + 1) <= i) ++l;
+        double p3 = 1.0;
+        for (int j = 0; j < l; ++j) p3 *= 3.0;
+        mark[i] = __dmul_rn(cells[i], dt) <= __ddiv_rn(1.0, p3) ? 1 : 0;
+    }
+}
+
+hipError_t launch_vmax(const pic_tree *t, int scheme, const pic_particles *p, const int64_t *bin_start, double dt,
+                       double *cells, uint8_t *quiet, void *scratch, hipStream_t s) {
+    const int L = t->inst[0].L, d = t->dim;
+    const int64_t nb = n_bins_of(t, scheme), nl = t->leaf_off.back();
+    double *bval = (double *)scratch;   // per-bin values
+    const int64_t n_cells = cell_off(d, L + 1);
+    F64Ptrs P = make_ptrs(t, p, nullptr, nullptr);
+    PIC_LAUNCH("fill", k_fill_cells, dim3(grid_for(n_cells, 256, 1 << 16)), dim3(256), 0, s,
+               (unsigned long long *)cells, quiet, n_cells);
+    if (nb > 0)
+        PIC_LAUNCH("vmax_bins", k_vmax_bins, dim3(grid_for(nb, 4, 1 << 16)), dim3(256), 0, s, P, d, bin_start, nb,
+                   bval);
+    if (d == 2)
+        PIC_LAUNCH("vmax_leaves", k_vmax_leaves<2>, dim3(grid_for(nl, 256, 1 << 16)), dim3(256), 0, s, t->dt, scheme,
+                   bval, nl, (unsigned long long *)cells, quiet);
+    else
+        PIC_LAUNCH("vmax_leaves", k_vmax_leaves<3>, dim3(grid_for(nl, 256, 1 << 16)), dim3(256), 0, s, t->dt, scheme,
+                   bval, nl, (unsigned long long *)cells, quiet);
+    if (quiet)
+        PIC_LAUNCH("vmax_quiet", k_vmax_quiet, dim3(grid_for(n_cells, 256, 1 << 16)), dim3(256), 0, s, cells, d, L,
+                   dt, quiet);
+    return hipGetLastError();
+}
+
+size_t vmax_scratch_bytes(const pic_tree *t, int scheme) {
+    return align256((size_t)n_bins_of(t, scheme) * sizeof(double));
+}
+
+int64_t vmax_cells(const pic_tree *t) { return cell_off(t->dim, t->inst[0].L + 1); }
+
 // ------------------------------------------------------ ppc-driven adaptation
 //
 // Per level a dense state byte for every cell position (the layout of the

@@ -145,3 +145,25 @@ def test_adaptive_runs_match_oracle(dim, box, scheme):
         assert run.tree.status_sync() == 0
     if box < 1.0:
         assert changes > 0           # the particles leave the sub-box: the tree follows
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("name", sorted(TREES))
+def test_vmax_matches_oracle(name, scheme):
+    """raPIDT's v_max per cell and its predicate (Sec. 5.4, Eq. (vmax)):
+    bit for bit against the oracle's definition, for several time steps."""
+    dev = _dev()
+    spec = TREES[name]()
+    rng = np.random.default_rng(17 + scheme)
+    n = 4000 + 33
+    x, v = _paper_particles(rng, spec.dim, n)
+    v[:, :5] *= 3.0                          # a few fast particles
+    run = pic.FreeStreamRun(pic.Tree(spec).upload(), scheme, x, v, device=dev)
+    run.initial_sort()
+    xs, vs = run.x.cpu().numpy(), run.v.cpu().numpy()
+    for dt in (1e-3, 0.05, 0.3):
+        got, quiet = run.vmax(dt)
+        want, wq = oracle.vmax_cells(spec, xs, vs, scheme, dt=dt)
+        assert np.array_equal(got.cpu().numpy(), np.concatenate(want))
+        assert np.array_equal(quiet.cpu().numpy(), np.concatenate(wq))
+    assert run.tree.status_sync() == 0

@@ -159,7 +159,7 @@ def test_pins_catch_adapt_mutant(name):
 VMAX_MUTANTS = {
     "pidt_from_own_leaf_only": ("per_leaf = per_bin[lv[\"pidt\"]].max(axis=1)", "np.maximum.at(per_leaf, leaf, speed)"),
     "leaves_only_no_ancestors": ("for up in range(l, -1, -1):", "for up in range(l, l - 1, -1):"),
-    "predicate_strict": ("out[l] * dt <= 3.0 ** -l", "out[l] * dt < 3.0 ** -l * 0.5"),
+    "predicate_strict": ("out[l] * dt <= 1.0 / 3 ** l", "out[l] * dt < 0.5 / 3 ** l"),
     "speed_from_axis0": ("speed = np.max(np.abs(np.asarray(v, np.float64)), axis=0)",
                          "speed = np.abs(np.asarray(v, np.float64))[0]"),
 }
