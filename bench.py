@@ -321,6 +321,15 @@ def run_batched(args, scheme):
 
     st = pic.Stepper32(t, scheme, x, v, inst_start=inst_start, dt_dev=dd, device=dev)
     timed_graph(st, "batched_f32")
+    lib.pic_profile_enable(1)
+    kernel_times(lib)
+    for _ in range(steps):
+        st.step_fused(E, 0.0, 0.0, **kw)
+    torch.cuda.synchronize()
+    kt32 = kernel_times(lib)
+    lib.pic_profile_enable(0)
+    results["batched_f32"]["kernels_ms"] = {k: round(tot / a, 4) for k, (a, tot) in
+                                            sorted(kt32.items(), key=lambda kv: -kv[1][1])}
     del st
     torch.cuda.empty_cache()
 

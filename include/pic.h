@@ -322,7 +322,9 @@ pic_status pic_deposit(const pic_tree *tree, int32_t scheme, int32_t precision,
 /*
  * One whole step in a single call: the same result as pic_gather_push, then
  * pic_rebin (in -> out) and pic_deposit (on out) (paper Sec. 3 steps 1, 3, 4;
- * Sec. 5 re-binning).  `in` stays unchanged: a key pass pushes every
+ * Sec. 5 re-binning).  `in` stays unchanged (unless the tree's knob
+ * "key_stores" makes the key pass store the pushed state there, in the old
+ * order: by default the FP32 form of 3D trees): a key pass pushes every
  * particle and writes its key 2 * new bin + arrived; a group pass ranks every particle among the particles of its tile with the
  * same key, in tile order; a scan and a placement give every run (tile, key)
  * its destination; an emit pass pushes each particle again (the same
@@ -418,6 +420,11 @@ pic_status pic_profile_only(const char *name);
  *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);
  *   "step_fuse"     1 = pic_step's key pass and tile ranking run as one kernel, 0 = as
  *                   a key pass that writes the keys and a ranking pass (default 0);
+ *   "key_stores"    1 = pic_step's key pass stores the pushed state back into `in`
+ *                   (x, v or off, u, in the old order) and the writing pass only
+ *                   moves it; 0 = the writing pass pushes again and `in` stays
+ *                   unchanged; 2 = 1 for the FP32 form of 3D trees, else 0
+ *                   (default 2; step_fuse 1 pushes again in any case);
  *   "group_match"   pic_step's ranking pass (step_fuse 0): 1 = lanes with equal keys
  *                   found by wavefront ballots, one table access per distinct key;
  *                   0 = every lane tags and masks its table slot (default 0);

@@ -281,6 +281,9 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
     } else if (k == "step_fuse") {
         if (!one_of({0, 1})) return false;
         g.step_fuse = (int)value;
+    } else if (k == "key_stores") {
+        if (!one_of({0, 1, 2})) return false;
+        g.key_stores = (int)value;
     } else if (k == "group_match") {
         if (!one_of({0, 1})) return false;
         g.group_match = (int)value;
@@ -309,6 +312,7 @@ int64_t tune_get(const Tuning &g, const char *name) {
     if (k == "step_fuse") return g.step_fuse;
     if (k == "emit_deposit") return g.emit_deposit;
     if (k == "group_match") return g.group_match;
+    if (k == "key_stores") return g.key_stores;
     if (k == "deposit_bpw") return g.deposit_bpw;
     return -1;
 }

@@ -285,14 +285,14 @@ __device__ __forceinline__ uint32_t old_bin_wave(const int64_t *start, uint32_t 
 
 // FP32 form, key pass of pic_step: one particle per thread, pushed, its key
 // 2*bin + arrived written out (a particle arrives iff its bin changes: the
-// bin is implicit in the segment it is stored in).  Clears the per-call
-// counters.
+// bin is implicit in the segment it is stored in); with `store` the pushed
+// offsets and velocities go back to the input arrays in place.
 template <int D, int SCHEME, bool MULTI>
 __global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
                                                       double dt0, const double *qa, const double *da,
                                                       const int64_t *inst_start, const int64_t *bin_start,
                                                       uint32_t n_bins, const uint32_t *tile_bin, int tile,
-                                                      uint32_t *key_out, const uint32_t *wave_bin) {
+                                                      uint32_t *key_out, const uint32_t *wave_bin, int store) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         int ii = 0;
@@ -315,6 +315,13 @@ __global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F3
         if (nb >= n_bins) bad |= PIC_DEV_RANGE;
         nb = min(nb, n_bins - 1u);
         key_out[p] = 2u * nb + (nb == ob ? 0u : 1u);
+        if (store) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                P.off[k][p] = o[k];
+                P.u[k][p] = u[k];
+            }
+        }
         if (bad) flag_status(t.status, bad);
     }
 }
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
                                                       uint32_t n_bins, const uint32_t *tile_bin,
                                                       const uint32_t *meta, const uint32_t *run_dest,
                                                       const uint32_t *run_info, F32Ptrs out, Cols extra, int xcd,
-                                                      const uint32_t *wave_bin) {
+                                                      const uint32_t *wave_bin, int pushed) {
     constexpr int IPT = TILE / NT;
     __shared__ uint64_t s_val[TILE];
     __shared__ uint32_t s_dst[TILE];
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
-        if (p >= n) continue;
+        if (pushed || p >= n) continue;   // pushed: the key pass stored the state
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
         const DevInst &in = MULTI ? t.inst[ii] : in0;
@@ -677,16 +684,17 @@ static void step_passes_f32(const pic_tree *t, const F32Ptrs &P, const F32Ptrs &
                             void *stats, hipStream_t s) {
     constexpr int TILE = 2048;
     const int64_t tiles = (n + TILE - 1) / TILE;
+    const int stored = t->tune.key_stores == 1 || (t->tune.key_stores == 2 && D == 3);
     PIC_LAUNCH("step_key_f32", (k_step_key_f32<D, SCH, MULTI>), dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
                t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
-               TILE, sc.keys, (const uint32_t *)sc.wave_bin);
+               TILE, sc.keys, (const uint32_t *)sc.wave_bin, stored);
     if (stats) (void)launch_rebin_stats(t, SCH, old_start, sc.keys, 1, n, stats, s);
     launch_group(sc.keys, n, TILE, t->tune.group_match != 0, sc, s);
     launch_step_middle(t, n, n_bins, sc, new_start, s);
     PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024>), dim3(tiles), dim3(1024), 0, s, t->dt,
                t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
                (const uint32_t *)sc.meta, (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, Q, extra,
-               t->tune.xcd_tiles, (const uint32_t *)sc.wave_bin);
+               t->tune.xcd_tiles, (const uint32_t *)sc.wave_bin, stored);
 }
 
 hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,

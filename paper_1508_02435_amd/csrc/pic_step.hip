@@ -12,14 +12,15 @@
 namespace pic {
 
 // Key pass of the unfused form: one particle per thread, pushed, its key
-// 2*bin + arrived written out (the state itself is not); it also clears the
-// per-call counters.
+// 2*bin + arrived written out; with `store` the pushed state also goes back
+// to the input arrays, in place, so that the writing pass only moves it.
+// It also clears the per-call counters.
 template <int D, int SCHEME, bool REG, bool MULTI>
 __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const int64_t *old_start,
                                                   uint32_t n_bins, uint32_t *key_out, uint32_t *zero,
-                                                  int64_t n_zero) {
+                                                  int64_t n_zero, int store) {
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
     const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -34,6 +35,13 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
         }
         key_out[p] = step_key_one<D, SCHEME, REG, MULTI>(t, in0, P, p, xv, vv, qmdt0, dt0, qa, da, inst_start,
                                                          old_start, n_bins, lds, lds_n, bad);
+        if (store) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                P.x[k][p] = xv[k];
+                P.v[k][p] = vv[k];
+            }
+        }
         if (bad) flag_status(t.status, bad);
     }
 }
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
                                                   const int64_t *inst_start, const uint32_t *meta,
                                                   const uint32_t *run_dest, const uint32_t *run_info,
                                                   const uint32_t *run_pos, double *run_part, F64Ptrs out,
-                                                  Cols extra, int xcd) {
+                                                  Cols extra, int xcd, int pushed) {
     constexpr int IPT = TILE / NT;
     constexpr int NW = NT / 64;
     constexpr int NSD = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     __shared__ uint32_t s_erid[DEP ? NW : 1][2];                // their run ids | VALID | CONT
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
-    const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int lds_n = (MULTI || pushed) ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
     const int cnt = (int)min((int64_t)TILE, n - lo);
     for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
@@ -283,10 +291,11 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
             if (dst[j] == ~0u) miss = 1;
         }
     }
+    // the state as the key pass pushed it: again here, or stored by it
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
-        if (!(full || p < n)) continue;
+        if (pushed || !(full || p < n)) continue;
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
         const DevInst &in = MULTI ? t.inst[ii] : in0;
@@ -401,12 +410,14 @@ struct StepArgs {
     PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP>), dim3(tiles), dim3(NT), 0, s, t->dt,  \
                t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,          \
                (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, (const uint32_t *)sc.run_pos,      \
-               sc.run_part, a.out, extra, t->tune.xcd_tiles)
+               sc.run_part, a.out, extra, t->tune.xcd_tiles, stored ? 1 : 0)
 
 template <int D, int SCH, bool REG, bool MULTI, int TILE>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + TILE - 1) / TILE;
+    // the key pass stores the pushed state (the fused key+rank kernel does not)
+    const bool stored = t->tune.key_stores == 1 && !t->tune.step_fuse;
     if (a.n > 0 && t->tune.step_fuse) {
         // counters cleared first; the key pass and the ranking are one kernel
         launch_prep(a.zero, a.n_zero, nullptr, a.n_bins, a.n, TILE, sc, s);
@@ -416,7 +427,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
     } else if (a.n > 0) {
         PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0, s,
                    t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
-                   sc.keys, a.zero, a.n_zero);
+                   sc.keys, a.zero, a.n_zero, stored ? 1 : 0);
         if (a.stats) (void)launch_rebin_stats(t, SCH, a.old_start, sc.keys, 1, a.n, a.stats, s);
         launch_group(sc.keys, a.n, TILE, t->tune.group_match != 0, sc, s);
     }

@@ -315,6 +315,8 @@ def test_fused_step_matches_oracle(name, scheme, kind):
 STEP_FORMS = [dict(step_fuse=f, group_match=gm, emit_threads=nt, xcd_tiles=x, step_tile=tl, emit_deposit=dep)
               for f, gm in ((1, 0), (0, 0), (0, 1)) for nt in (1024, 512) for x in (1, 0) for tl in (2048, 1024)
               for dep in (1, 0)]
+STEP_FORMS += [dict(step_fuse=0, group_match=0, emit_threads=nt, xcd_tiles=1, step_tile=tl, emit_deposit=dep,
+                    key_stores=1) for nt in (1024, 512) for tl in (2048, 1024) for dep in (1, 0)]
 
 
 @pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
