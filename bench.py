@@ -51,29 +51,32 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_f32(dim: int, per_particle_q: bool):
-    """Bytes each kernel must move per particle (FP32 offset form)."""
+def algorithmic_bytes_f32(dim: int, per_particle_q: bool, stored: bool = False):
+    """Bytes each kernel must move per particle (FP32 offset form); `stored`:
+    the key pass writes the pushed state back (knob key_stores)."""
     s_push = 2 * 4 * dim                   # off, u
     q = 8 if per_particle_q else 0
     s_rec = s_push + q
     s_dep = 4 * dim + q
+    key = s_push + 4 + (s_push if stored else 0)   # off, u read, key (and the pushed state) written
     return {
         "gather_push_f32": 2 * s_push + 4,
         "rebin_tiles": 4,
         "rebin_scatter": 2 * s_rec,
         "deposit_bins_f32": s_dep,
-        "step_key_f32": s_push + 4,            # off, u read, key written
+        "step_key_f32": key,
         "step_group": 4 + 4,
         "step_emit_f32": s_push + 4 + s_rec + q,
-        "fused": (s_push + 4) + 8 + (s_push + 4 + s_rec + q) + s_dep,
+        "fused": key + 8 + (s_push + 4 + s_rec + q) + s_dep,
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
     }
 
 
-def algorithmic_bytes(dim: int, per_particle_q: bool):
+def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False):
     """Bytes each kernel must move per particle (FP64 form).  "calls" is the
     three-call path (gather_push, rebin, deposit); "fused" is pic_step (key,
-    group and emit passes, then the deposit)."""
+    group and emit passes, then the deposit); `stored`: the key pass writes
+    the pushed state back (knob key_stores)."""
     s_push = 2 * 8 * dim                   # x, v
     q = 8 if per_particle_q else 0
     s_rec = s_push + q                     # a full record moved by a rebin
@@ -83,7 +86,7 @@ def algorithmic_bytes(dim: int, per_particle_q: bool):
         "rebin_tiles": 4,                  # new bins read
         "rebin_scatter": 2 * s_rec,        # every record read and written once
         "deposit_bins": s_dep,
-        "step_key": s_push + 4,            # x, v read, key written
+        "step_key": s_push + 4 + (s_push if stored else 0),   # x, v read, key (and the pushed state) written
         "step_group": 4 + 4,               # key read, run index | rank written
         "step_emit": s_push + 4 + s_rec + q,   # x, v, run index | rank (and q) read, the record written
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
@@ -130,23 +133,30 @@ def cpu_baseline(wl, scheme, sample, E_np, min_seconds=10.0, max_steps=8):
                       f"{os.cpu_count()} logical CPUs visible"}
 
 
+def source_digest() -> str:
+    """sha256 over every kernel source and the ABI header, in name order: the
+    stored counter figures hold only for the sources they were taken with."""
+    import glob
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1508_02435_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "pic.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if still valid."""
+    """HBM bytes per launch from committed rocprofv3 counter runs, if still
+    valid (taken with the current kernel sources)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent:
-        return None
-    src = os.path.join(ROOT, ent["source"])
-    try:
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    if digest != ent.get("source_sha256"):
-        return None                       # the kernel changed since the counters were taken
+    if not ent or ent.get("source_digest") != source_digest():
+        return None                       # a kernel changed since the counters were taken
     return ent["bytes_per_launch"]
 
 
@@ -586,7 +596,10 @@ def main():
         return st
 
     accuracy = fp32_accuracy(pic, torch, tree, scheme, wl, x0_host, v0_host, fields[0], dev) if f32 else None
-    ab = algorithmic_bytes_f32(wl.dim, wl.q is not None) if f32 else algorithmic_bytes(wl.dim, wl.q is not None)
+    ks = pic.tuning(tree)["key_stores"]
+    stored = args.path == "fused" and (ks == 1 or (ks == 2 and f32 and wl.dim == 3))
+    ab = algorithmic_bytes_f32(wl.dim, wl.q is not None, stored) if f32 else \
+        algorithmic_bytes(wl.dim, wl.q is not None, stored)
     lib = pic.lib()
     st = fresh()
     step = st.step_fused if args.path == "fused" else st.step
