@@ -444,7 +444,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
 // ------------------------------------------------------------------- rebin
 
 constexpr int RB_THREADS = 256;
-constexpr int KLIST_CAP = 128;  // runs per key listed directly by the fused step's ranking
+constexpr int KLIST_CAP = 128;  // most runs per key listed directly by the fused step's ranking
 constexpr int RB_MAX_TILE = 4096;
 
 struct RebinScratch {
@@ -466,13 +466,14 @@ struct RebinScratch {
     uint64_t *run_wcnt;   // n_tiles * TILE: fused step, 16-bit count per wavefront
     uint32_t *meta;       // n_tiles * TILE: fused step, run index | rank << 16 per particle
     uint32_t *keys;       // n_tiles * TILE: fused step (three-pass form), key per particle
-    uint32_t *klist;      // 2*n_bins * KLIST_CAP: fused step, run addresses per key (arrival order)
-    uint32_t *khead;      // 2*n_bins (zeroed per call): runs of a key past KLIST_CAP, a linked list
+    uint32_t *klist;      // 2*n_bins * klist_cap: fused step, run addresses per key (arrival order)
+    uint32_t *khead;      // 2*n_bins (zeroed per call): runs of a key past klist_cap, a linked list
     uint32_t *knext;      // n_tiles * TILE: next run of that list (run address + 1; 0 ends it)
     uint32_t *wave_bin;   // n_tiles * TILE / 64: old bin of slot 64 c (sorted input), for the FP32 form
     uint32_t *run_pos;    // n_tiles * TILE: fused step, a run's position among all runs sorted by (key, tile)
     double *run_part;     // fused step with the deposit in the writing pass: per run (by run_pos) its
                           // particles' summed weights, ns doubles
+    uint32_t klist_cap;   // runs per key in the direct list (16..KLIST_CAP, from particles per key)
 };
 
 // Scan shapes: the three-call re-bin scans SCAN_TILE keys per block, the

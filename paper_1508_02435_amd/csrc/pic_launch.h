@@ -37,6 +37,7 @@ struct RebinLayout {
         list_off,
         list, scan_state, scan_ctr, khead, run_wcnt, meta, keys, klist, knext, wave_bin, run_pos, run_part, bin_part,
         total;
+    uint32_t klist_cap;
 };
 
 // run_ns: doubles of each run's deposit partial when the writing pass of the
@@ -67,7 +68,13 @@ inline RebinLayout rebin_layout(int64_t n, int64_t n_bins, int tile, int run_ns 
     L.run_wcnt = o; o = align256(o + slots * 8);
     L.meta = o; o = align256(o + slots * 4);
     L.keys = o; o = align256(o + slots * 4);
-    L.klist = o; o = align256(o + keys * KLIST_CAP * 4);
+    // the direct run list of a key: four times the slots per key, rounded up
+    // to a power of two, between 16 and KLIST_CAP (a denser key spills into
+    // the linked rest)
+    uint32_t cap = 16;
+    while (cap < (uint32_t)KLIST_CAP && (int64_t)cap * keys < 4 * slots) cap *= 2;
+    L.klist_cap = cap;
+    L.klist = o; o = align256(o + keys * (int64_t)cap * 4);
     L.knext = o; o = align256(o + slots * 4);
     L.wave_bin = o; o = align256(o + (slots / 64 + 1) * 4);
     L.run_pos = o; o = align256(o + slots * 4);
@@ -103,6 +110,7 @@ inline RebinScratch bind_scratch(const RebinLayout &L, char *base) {
     sc.wave_bin = (uint32_t *)(base + L.wave_bin);
     sc.run_pos = (uint32_t *)(base + L.run_pos);
     sc.run_part = (double *)(base + L.run_part);
+    sc.klist_cap = L.klist_cap;
     return sc;
 }
 

@@ -161,7 +161,7 @@ __device__ __forceinline__ void tile_compact(SM &S, int64_t tile, int64_t lo, co
     for (int e = 0; e < IPT; ++e) {
         if (!k1[e]) continue;
         const uint32_t k = k1[e] - 1u, a = (uint32_t)lo + rr[e];
-        if (pos[e] < (uint32_t)KLIST_CAP) sc.klist[(int64_t)k * KLIST_CAP + pos[e]] = a;
+        if (pos[e] < sc.klist_cap) sc.klist[(int64_t)k * sc.klist_cap + pos[e]] = a;
         else sc.knext[a] = atomicExch(&sc.khead[k], a + 1u);
     }
     __syncthreads();
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_step_group_match(const uint32_t 
 // (count, runs) pairs of SP_KEYS keys; its first wavefront publishes the
 // block's aggregate and looks back over up to 64 predecessors at a time (one
 // lane per predecessor) for the exclusive prefix.  Place: per key, its runs
-// (the direct list the ranking filled, then for keys with more than KLIST_CAP
+// (the direct list the ranking filled, then for keys with more than klist_cap
 // runs the linked rest) sorted by run address, i.e. tile order, and given
 // their destinations.
 
@@ -560,28 +560,29 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
             lo = sc.list_off[key];
         }
         if (__ballot(len != 0u) == 0) continue;   // four empty keys
-        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * KLIST_CAP), len, kb, sub, sc.run_pos, lo);
+        const uint32_t cap = sc.klist_cap;        // >= 16
+        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * cap), len, kb, sub, sc.run_pos, lo);
         for (int g = 0; g < 4; ++g) {
             const int64_t gk = k0 + g;
             const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
             const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
             const uint32_t glo = (uint32_t)__shfl((int)lo, g * 16, 64);
             if (glen <= 16) continue;
-            if (glen <= 64u) {
-                place_sorted<64>(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane, sc.run_pos, glo);
+            if (glen <= 64u && glen <= cap) {
+                place_sorted<64>(sc, sc.klist, (uint32_t)(gk * cap), glen, gkb, lane, sc.run_pos, glo);
                 continue;
             }
-            if (glen <= (uint32_t)KLIST_CAP) {
-                place_counted(sc, sc.klist, (uint32_t)(gk * KLIST_CAP), glen, gkb, lane, glo);
+            if (glen <= cap) {
+                place_counted(sc, sc.klist, (uint32_t)(gk * cap), glen, gkb, lane, glo);
                 continue;
             }
             // a long list: gathered into its exact slot range of the list
             // array (direct part by the lanes, linked part by lane 0), then
             // every run counts the runs before it
             const uint32_t l0 = glo;
-            for (int i = lane; i < KLIST_CAP; i += 64) sc.list[l0 + i] = sc.klist[gk * KLIST_CAP + i];
+            for (uint32_t i = lane; i < cap; i += 64) sc.list[l0 + i] = sc.klist[gk * cap + i];
             if (lane == 0) {
-                uint32_t q = KLIST_CAP;
+                uint32_t q = cap;
                 for (uint32_t e = sc.khead[gk]; e != 0u && q < glen; e = sc.knext[e - 1u]) sc.list[l0 + q++] = e - 1u;
             }
             __threadfence();   // lane 0's entries visible to the other lanes' loads

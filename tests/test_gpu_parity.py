@@ -624,3 +624,47 @@ def test_writing_pass_deposit_with_long_runs_and_ragged_tiles(scheme, n, step_ti
     finally:
         for k, val in saved.items():
             pic.tune(k, val)
+
+
+@pytest.mark.parametrize("clusters,spread,most", [(4, 0.0005, 16), (1, 0.0001, 64)])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_fused_step_with_short_direct_run_lists(scheme, clusters, spread, most):
+    """A sparse set on a large tree (200k particles, 59,049 leaves) gets
+    direct run lists of 16 per key; the particles sit in a few cells, so
+    their keys collect runs from many tiles and spill into the linked
+    overflow (from 17 runs on; past 64 with one cluster).  The step still
+    matches the oracle."""
+    dev = _dev()
+    rng = np.random.default_rng(71 + scheme)
+    spec = W.regular_tree(2, 5)
+    n = 200_000
+    centres = rng.random((2, clusters))
+    x = (centres[:, rng.integers(0, clusters, n)] + spread * rng.standard_normal((2, n))) % 1.0
+    x[x >= 1.0] = 0.0
+    v = 0.002 * rng.standard_normal((2, n))
+    o = oracle.OracleTree(spec)
+    t = _tree(spec)
+    E = W.random_field(rng, 2, o.n_vertices, 0.01)
+    st = pic.Stepper(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+    st.initial_sort()
+    xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+    # the case is the one meant: in the first step some key (a stayer key of
+    # the sorted input) has more runs than the direct list holds
+    tile = pic.tuning()["step_tile"]
+    old_bin = np.repeat(np.arange(len(start) - 1), np.diff(start))
+    runs = {}
+    for a in range(0, n, tile):
+        for k in np.unique(old_bin[a:a + tile]):
+            runs[k] = runs.get(k, 0) + 1
+    assert max(runs.values()) > most
+    for _ in range(2):
+        st.step_fused(torch.tensor(E, device=dev), -0.5, 0.5, q_uniform=-1.0 / n)
+        r = oracle.step(o, xs, vs, E, -0.5, 0.5, start, scheme, None, -1.0 / n)
+        torch.cuda.synchronize()
+        ids = ids[r["perm"]]
+        assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+        assert np.array_equal(st.ids.cpu().numpy(), ids)
+        assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+        _check_rho(st.rho.cpu().numpy(), r["rho"])
+        xs, vs, start = r["x"], r["v"], r["bin_start"]
+    assert t.status_sync() == 0
