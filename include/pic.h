@@ -425,9 +425,10 @@ pic_status pic_profile_only(const char *name);
  *                   moves it; 0 = the writing pass pushes again and `in` stays
  *                   unchanged; 2 = 1 for the FP32 form of 3D trees, else 0
  *                   (default 2; step_fuse 1 pushes again in any case);
- *   "group_match"   pic_step's ranking pass (step_fuse 0): 1 = lanes with equal keys
- *                   found by wavefront ballots, one table access per distinct key;
- *                   0 = every lane tags and masks its table slot (default 0);
+ *   "group_match"   pic_step's ranking pass (step_fuse 0): 0 = every lane tags and
+ *                   masks its table slot; 1 = lanes of equal keys found by
+ *                   wavefront ballots, one table access per distinct key
+ *                   (default 0);
  *   "emit_deposit"  1 = for 2D single trees whose instances are regular and a uniform
  *                   charge, pic_step's writing pass sums each run's weights while
  *                   the run is in LDS and the deposit only adds runs per bin; 0 = the

@@ -2,7 +2,8 @@
 
 The launch-shape knobs of libpic (tile sizes of the re-bin and of the fused
 step, radix width, scatter staging and grouping, threads of the writing pass,
-lanes per deposit bin) never change results; they only change speed, and the best values depend on the
+lanes and bins per deposit group, where the pushed state and the deposit are
+computed, the ranking form) never change the re-binned state; they only change speed, and the best values depend on the
 workload (dimension, particles per bin, how far particles move, how many
 instances a forest holds).  ``autotune`` times every setting of the knobs that
 matter for the chosen path on the actual state, restores the state after each
@@ -20,11 +21,14 @@ from . import Stepper32, tune, tuning
 
 # knobs each path depends on
 SPACES = {
+    # tile size, threads of the writing pass, lanes per deposit bin and bins
+    # per lane group (the deposit's bucket), the writing-pass deposit, the
+    # stored push, the ranking form
     "fused_f64": {"step_tile": (2048, 1024), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16),
-                  "emit_deposit": (0, 1)},
+                  "deposit_bpw": (1, 2), "emit_deposit": (0, 1), "key_stores": (2, 1), "group_match": (0, 1)},
     "calls_f64": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1), "deposit_lanes": (64, 32, 16)},
-    "f32": {"xcd_tiles": (1, 0)},
+    "f32": {"xcd_tiles": (1, 0), "key_stores": (2, 1, 0), "group_match": (0, 1)},
     "calls_f32": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1)},
 }
