@@ -317,14 +317,12 @@ def adapt(tree: Tree, leaf_count, ppc: int, max_level: int):
     cnt = np.ascontiguousarray(np.asarray(leaf_count, dtype=np.int64))
     _need(cnt.shape == (tree.n_leaves,), "leaf_count needs one entry per leaf")
     ln, nl = C.c_size_t(0), C.c_int32(0)
-    st = lib().pic_tree_adapt(tree.handle, cnt.ctypes.data, int(ppc), int(max_level), None, 0, C.byref(ln),
-                              C.byref(nl))
-    if st not in (_capi.PIC_OK, _capi.PIC_E_CAPACITY):
-        check(st, "pic_tree_adapt")
-    masks = np.zeros(max(ln.value, 1), np.uint8)
+    L0, d = tree.specs[0].max_level, tree.dim
+    deepest = max(L0, min(L0 + 1, int(max_level)))
+    masks = np.zeros(max(sum(3 ** (d * lev) for lev in range(deepest)), 1), np.uint8)
     check(lib().pic_tree_adapt(tree.handle, cnt.ctypes.data, int(ppc), int(max_level), masks.ctypes.data,
                                masks.size, C.byref(ln), C.byref(nl)), "pic_tree_adapt")
-    L, d = nl.value, tree.dim
+    L = nl.value
     levels, off = [], 0
     for lev in range(L):
         k = 3 ** (d * lev)

@@ -277,85 +277,62 @@ int64_t vmax_cells(const pic_tree *t) { return cell_off(t->dim, t->inst[0].L + 1
 // refine masks): 0 absent, 1 leaf, 2 refined, 3 leaf to refine, 4 refined
 // cell to coarsen.  Leaves come from the tree's leaf table (level and
 // coordinates per Peano rank); every ancestor of a leaf is refined.
-namespace {
-
-int64_t lex_of(int dim, int64_t n, const int64_t *a) {
-    int64_t r = 0, m = 1;
-    for (int k = 0; k < dim; ++k) {
-        r += a[k] * m;
-        m *= n;
-    }
-    return r;
-}
-
-}  // namespace
 
 pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int max_level,
                        std::vector<uint8_t> &masks, int &new_L) {
     const pic::HostInst &h = t->inst[0];
     const int d = t->dim, L = h.L;
     const int top = std::max(L, std::min(L + 1, max_level));   // deepest level the new tree can reach
+    int64_t p3[64];
+    p3[0] = 1;
+    for (int i = 1; i < 64; ++i) p3[i] = p3[i - 1] * 3;
+    auto lex = [&](int l, const int64_t *a) {
+        int64_t r = 0;
+        for (int k = d - 1; k >= 0; --k) r = r * p3[l] + a[k];
+        return r;
+    };
     std::vector<std::vector<uint8_t>> st(top + 1);
-    for (int l = 0; l <= top; ++l) st[l].assign((size_t)pow3_u64(d * l), 0);
-    std::unordered_map<int64_t, int64_t> cnt;   // (level, lex) -> particles, leaves only
+    for (int l = 0; l <= top; ++l) st[l].assign((size_t)p3[d * l], 0);
+    // per parent of a leaf: (its leaf children, their particles)
+    std::unordered_map<int64_t, std::pair<int, int64_t>> kids;
     const int64_t nl = (int64_t)h.leaf_level.size();
+    kids.reserve((size_t)(nl / 4 + 16));
     for (int64_t r = 0; r < nl; ++r) {
         const int l = h.leaf_level[r];
         int64_t a[3];
         for (int k = 0; k < d; ++k) a[k] = h.leaf_coord[(size_t)r * d + k];
-        const int64_t id = lex_of(d, pow3_u64(l), a);
-        st[l][id] = 1;
-        cnt[id * 32 + l] = leaf_count[r];
-        for (int up = l - 1; up >= 0; --up) {
+        const int64_t id = lex(l, a);
+        // refine: an overfull leaf above the level cap
+        st[l][id] = (l < max_level && leaf_count[r] > ppc) ? 3 : 1;
+        if (l >= 2) {
+            int64_t b[3];
+            for (int k = 0; k < d; ++k) b[k] = a[k] / 3;
+            auto &e = kids[lex(l - 1, b) * 32 + (l - 1)];
+            e.first += 1;
+            e.second += leaf_count[r];
+        }
+        for (int up = l - 1; up >= 0; --up) {   // every ancestor is refined
             for (int k = 0; k < d; ++k) a[k] /= 3;
-            uint8_t &s = st[up][lex_of(d, pow3_u64(up), a)];
+            uint8_t &s = st[up][lex(up, a)];
             if (s == 2) break;
             s = 2;
         }
     }
-    auto count_of = [&](int l, int64_t id) -> int64_t {
-        auto it = cnt.find(id * 32 + l);
-        return it == cnt.end() ? 0 : it->second;
-    };
-    // refine: overfull leaves above the level cap
-    for (int l = 0; l <= L && l < max_level; ++l)
-        for (size_t i = 0; i < st[l].size(); ++i)
-            if (st[l][i] == 1 && count_of(l, (int64_t)i) > ppc) st[l][i] = 3;
-    // coarsen: refined non-root cells whose children are all leaves (none of
-    // them being refined) holding together at most ppc particles
-    for (int l = 1; l < L; ++l) {
-        const int64_t n = pow3_u64(l);
-        for (size_t i = 0; i < st[l].size(); ++i) {
-            if (st[l][i] != 2) continue;
-            int64_t a[3], r = (int64_t)i;
-            for (int k = 0; k < d; ++k) {
-                a[k] = r % n;
-                r /= n;
-            }
-            bool leaves = true;
-            int64_t sum = 0;
-            const int nkid = (int)pow3_u64(d);
-            for (int c = 0; c < nkid && leaves; ++c) {
-                int64_t b[3], cc = c;
-                for (int k = 0; k < d; ++k) {
-                    b[k] = 3 * a[k] + cc % 3;
-                    cc /= 3;
-                }
-                const int64_t id = lex_of(d, 3 * n, b);
-                if (st[l + 1][id] != 1) leaves = false;
-                else sum += count_of(l + 1, id);
-            }
-            if (leaves && sum <= ppc) st[l][i] = 4;
-        }
+    // coarsen: a refined non-root cell whose 3^d children are all leaves
+    // (none of them refined by the rule above) holding at most ppc particles
+    // (a child being refined holds more than ppc by itself, so a cell whose
+    // children hold at most ppc has none)
+    for (const auto &kv : kids) {
+        const int l = (int)(kv.first & 31);
+        const int64_t id = kv.first >> 5;
+        if (kv.second.first == (int)p3[d] && kv.second.second <= ppc && st[l][id] == 2) st[l][id] = 4;
     }
     // the new masks: a cell is refined iff it is reached through refined
     // cells and is refined (2) or to be refined (3)
     std::vector<std::vector<uint8_t>> ref(top + 1);
-    ref[0].assign(1, 0);
     std::vector<uint8_t> live(1, 1);
     new_L = 0;
     for (int l = 0; l <= top; ++l) {
-        const int64_t n = pow3_u64(l);
         std::vector<uint8_t> m(st[l].size(), 0);
         bool any = false;
         for (size_t i = 0; i < m.size(); ++i)
@@ -364,25 +341,24 @@ pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc
                 any = true;
             }
         if (!any) break;
-        ref[l] = m;
+        ref[l].swap(m);
         new_L = l + 1;
         if (l + 1 > top) break;
-        std::vector<uint8_t> nxt((size_t)pow3_u64(d * (l + 1)), 0);
-        for (size_t i = 0; i < m.size(); ++i) {
-            if (!m[i]) continue;
+        std::vector<uint8_t> nxt((size_t)p3[d * (l + 1)], 0);
+        for (size_t i = 0; i < ref[l].size(); ++i) {
+            if (!ref[l][i]) continue;
             int64_t a[3], r = (int64_t)i;
             for (int k = 0; k < d; ++k) {
-                a[k] = r % n;
-                r /= n;
+                a[k] = r % p3[l];
+                r /= p3[l];
             }
-            const int nkid = (int)pow3_u64(d);
-            for (int c = 0; c < nkid; ++c) {
+            for (int c = 0; c < (int)p3[d]; ++c) {
                 int64_t b[3], cc = c;
                 for (int k = 0; k < d; ++k) {
                     b[k] = 3 * a[k] + cc % 3;
                     cc /= 3;
                 }
-                nxt[lex_of(d, 3 * n, b)] = 1;
+                nxt[lex(l + 1, b)] = 1;
             }
         }
         live.swap(nxt);
