@@ -488,6 +488,24 @@ pic_status pic_free_stream(const pic_tree *tree, int32_t scheme, int32_t precisi
                            uint32_t *bin_dev, void *stream);
 
 /*
+ * The same step as pic_free_stream then pic_rebin (in -> out), in the
+ * passes of pic_step: a key pass streams every particle (with the
+ * artificial flops) and writes its key 2 * new bin + arrived, the ranking,
+ * scan and placement give every (tile, key) run its destination, and a
+ * writing pass streams each particle again (the same arithmetic without the
+ * flops, so the same state and bin) and writes it there; no deposit.  The
+ * result (out, new_bin_start, stats) equals the two calls' bit for bit.
+ * Single trees (PIC_E_ARG for forests), FP64 form; the arguments as in
+ * pic_free_stream and pic_step (`in` stays unchanged unless the tree's knob
+ * "key_stores" is 1).  Scratch: pic_scratch_bytes().
+ */
+pic_status pic_stream_step(const pic_tree *tree, int32_t scheme, pic_particles *in, const int64_t *bin_start_dev,
+                           double dt, int32_t boundary, int32_t flops, int32_t n_extra, void *const *extra_in_dev,
+                           void *const *extra_out_dev, const int32_t *extra_bytes, pic_particles *out,
+                           int64_t *new_bin_start_dev, void *scratch_dev, size_t scratch_bytes,
+                           pic_rebin_stats *stats_dev, void *stream);
+
+/*
  * Particles per leaf: count_dev (device, forest-wide leaf count entries of
  * uint64) is overwritten with the number of particles of p whose position
  * lies in each leaf (the PIT bin, Theorem 1).  Any order of p.  For a set

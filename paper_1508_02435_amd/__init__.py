@@ -278,6 +278,34 @@ def free_stream(tree: Tree, scheme: int, x, v, dt: float, boundary: int, flops: 
           "pic_free_stream")
 
 
+def stream_step(tree: Tree, scheme: int, x, v, dt: float, boundary: int, flops: int, bin_start, x_out, v_out,
+                new_start, scratch, extra_in=(), extra_out=(), stats=None, stream=None):
+    """Free streaming and the stable re-bin in one call (the passes of
+    pic_step, no deposit); x, v are the sorted input, x_out/v_out receive
+    the re-binned set."""
+    n = x.shape[1]
+    for a, nm in ((x, "x"), (v, "v"), (x_out, "x_out"), (v_out, "v_out")):
+        _check_soa(a, tree.dim, n, "float64", nm)
+    nb = tree.n_bins(scheme)
+    _check_vec(bin_start, nb + 1, "bin_start")
+    _check_vec(new_start, nb + 1, "new_start")
+    _need(len(extra_in) == len(extra_out), "extra column lists differ in length")
+    for a, b in zip(extra_in, extra_out):
+        _check_vec(a, n, "extra in")
+        _check_vec(b, n, "extra out")
+    P = _particles(n, x=x, v=v)
+    Q = _particles(n, x=x_out, v=v_out)
+    ne = len(extra_in)
+    ins = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_in])
+    outs = (C.c_void_p * max(ne, 1))(*[_ptr(c) for c in extra_out])
+    sizes = (C.c_int32 * max(ne, 1))(*[c.element_size() for c in extra_in])
+    check(lib().pic_stream_step(tree.handle, scheme, C.byref(P), C.c_void_p(_ptr(bin_start)), float(dt),
+                                int(boundary), int(flops), ne, ins, outs, sizes, C.byref(Q),
+                                C.c_void_p(_ptr(new_start)), C.c_void_p(_ptr(scratch)),
+                                scratch.numel() * scratch.element_size(), _stats_ptr(stats),
+                                C.c_void_p(_stream(stream))), "pic_stream_step")
+
+
 def leaf_counts(tree: Tree, x, count_out, inst_start=None, stream=None):
     """Particles per leaf of an FP64 set (any order) into count_out (int64
     device tensor, one entry per leaf)."""
@@ -525,8 +553,17 @@ class FreeStreamRun(Stepper):
         free_stream(self.tree, self.scheme, self.x, self.v, dt, boundary, flops, self.bin)
 
     def step_free(self, dt: float, boundary: int = _capi.REFLECTING, flops: int = 0, stats=None):
+        """Free streaming, then the re-bin (two calls)."""
         self.move(dt, boundary, flops)
         self.rebin(stats)
+
+    def step_free_fused(self, dt: float, boundary: int = _capi.REFLECTING, flops: int = 0, stats=None):
+        """The same step in one call (pic_stream_step)."""
+        extra_in = [self.ids] if self.ids is not None else []
+        extra_out = [self.ids2] if self.ids is not None else []
+        stream_step(self.tree, self.scheme, self.x, self.v, dt, boundary, flops, self.start, self.x2, self.v2,
+                    self.start2, self.scratch, extra_in, extra_out, stats=stats)
+        self._swap()
 
     def leaf_counts(self):
         """Particles per leaf (host int64 array): the PIT bin offsets, or the

@@ -21,7 +21,7 @@ EXPORTS = [
     "pic_rebin", "pic_deposit", "pic_stream_push", "pic_profile_enable", "pic_profile_read",
     "pic_tune_set", "pic_tune_get", "pic_step", "pic_profile_only", "pic_convert",
     "pic_tree_tune_set", "pic_tree_tune_get", "pic_deposit_noalloc",
-    "pic_free_stream", "pic_leaf_counts", "pic_tree_adapt", "pic_vmax",
+    "pic_free_stream", "pic_leaf_counts", "pic_tree_adapt", "pic_vmax", "pic_stream_step",
 ]
 PERIODIC, REFLECTING = 0, 1   # PIC_PERIODIC, PIC_REFLECTING
 NOALLOC_SCRATCH_BYTES = 64 << 20   # PIC_NOALLOC_SCRATCH_BYTES
@@ -107,6 +107,9 @@ def lib():
         L.pic_tree_adapt.restype = i32
         L.pic_vmax.argtypes = [vp, i32, C.POINTER(Particles), vp, dbl, vp, vp, vp, sz, vp]
         L.pic_vmax.restype = i32
+        L.pic_stream_step.argtypes = [vp, i32, C.POINTER(Particles), vp, dbl, i32, i32, i32, vp, vp, vp,
+                                      C.POINTER(Particles), vp, vp, sz, vp, vp]
+        L.pic_stream_step.restype = i32
         L.pic_scratch_bytes.argtypes = [vp, i64, i32, i32]
         L.pic_scratch_bytes.restype = sz
         L.pic_rebin.argtypes = [vp, i32, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, vp]

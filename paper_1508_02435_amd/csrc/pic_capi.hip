@@ -676,6 +676,40 @@ pic_status pic_step(const pic_tree *t, int32_t scheme, int32_t precision, pic_pa
     return e == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
+pic_status pic_stream_step(const pic_tree *t, int32_t scheme, pic_particles *in, const int64_t *bin_start, double dt,
+                           int32_t boundary, int32_t flops, int32_t n_extra, void *const *extra_in,
+                           void *const *extra_out, const int32_t *extra_bytes, pic_particles *out,
+                           int64_t *new_bin_start, void *scratch, size_t scratch_bytes, pic_rebin_stats *stats,
+                           void *stream) {
+    if (!t || t->n_inst != 1 || !valid_scheme(scheme) || !particles_ok(t, in, PIC_F64, true) || !out)
+        return PIC_E_ARG;
+    if (out->n != in->n || !particles_ok(t, out, PIC_F64, true)) return PIC_E_ARG;
+    if (boundary != PIC_PERIODIC && boundary != PIC_REFLECTING) return PIC_E_ARG;
+    if (flops < 0 || flops > (1 << 20) || (flops & 1)) return PIC_E_ARG;
+    if (in->n > 0 && !bin_start) return PIC_E_ARG;
+    if (in->n > 0)
+        for (int k = 0; k < t->dim; ++k)
+            if (in->x[k] == out->x[k] || in->v[k] == out->v[k]) return PIC_E_ARG;
+    if (!new_bin_start || !scratch) return PIC_E_ARG;
+    if (n_extra < 0 || n_extra > 16 - 2 * t->dim) return PIC_E_ARG;
+    if (n_extra > 0 && (!extra_in || !extra_out || !extra_bytes)) return PIC_E_ARG;
+    Cols ex{};
+    ex.n = n_extra;
+    for (int i = 0; i < n_extra; ++i) {
+        if (extra_bytes[i] != 4 && extra_bytes[i] != 8) return PIC_E_ARG;
+        if (in->n > 0 && (!extra_in[i] || !extra_out[i] || extra_in[i] == extra_out[i])) return PIC_E_ARG;
+        ex.in[i] = extra_in[i];
+        ex.out[i] = extra_out[i];
+        ex.bytes[i] = extra_bytes[i];
+    }
+    if (scratch_bytes < pic_scratch_bytes(t, in->n, scheme, PIC_F64)) return PIC_E_SCRATCH;
+    if (!t->dev) return PIC_E_STATE;
+    return launch_stream_step(t, scheme, in, bin_start, dt, boundary, flops, ex, out, new_bin_start, scratch,
+                              scratch_bytes, stats, (hipStream_t)stream) == hipSuccess
+               ? PIC_OK
+               : PIC_E_HIP;
+}
+
 pic_status pic_convert(const pic_tree *t, int32_t scheme, int32_t to_precision, pic_particles *p, double dt,
                        const pic_push_params *params, const int64_t *bin_start, uint32_t *bin, void *stream) {
     if (!t || !valid_scheme(scheme) || !t->reg_kernels) return PIC_E_ARG;

@@ -362,6 +362,62 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
     return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
 }
 
+// One axis of a free-streaming move: x + v dt, then the wall rule.  Periodic:
+// x - floor(x), 1 -> 0 (the push's wrap).  Reflecting: mirrored at 0 (x ->
+// -x) or at 1 (x -> 2 - x, exact for x in [1, 2)), with the velocity
+// component negated; a landing exactly on 1 goes to the largest double below
+// 1.  A move that one mirror cannot bring back into the box is flagged and
+// clamped (the bin stays in range).
+template <int BC>
+__device__ __forceinline__ void stream_axis(double &x, double &v, double dt, uint32_t &bad) {
+    double y = __dadd_rn(x, __dmul_rn(v, dt));
+    if (BC == PIC_PERIODIC) {
+        y = __dsub_rn(y, floor(y));
+        if (y == 1.0) y = 0.0;
+    } else if (y < 0.0) {
+        y = -y;
+        v = -v;
+    } else if (y >= 1.0) {
+        y = __dsub_rn(2.0, y);
+        v = -v;
+        if (y == 1.0) y = 0x1.fffffffffffffp-1;
+    }
+    if (!(y >= 0.0 && y < 1.0)) {
+        bad |= (y - y == 0.0) ? PIC_DEV_RANGE : PIC_DEV_NONFINITE;
+        y = (y >= 1.0) ? 0x1.fffffffffffffp-1 : 0.0;
+    }
+    x = y;
+}
+
+// A free-streaming move of one particle (the particle-handling benchmark):
+// stream_axis per axis, then `flops` artificial operations (a dependent
+// multiply-add chain whose result only feeds a test that never holds); with
+// KEY the particle's new bin (the bin locate gives).
+template <int D, int SCHEME, bool REG, int BC, bool KEY>
+__device__ __forceinline__ uint32_t stream_one(const DevTree &t, const DevInst &in, const int32_t *lds, int lds_n,
+                                               double (&xv)[D], double (&vv)[D], double dt, int flops,
+                                               uint32_t &bad) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) stream_axis<BC>(xv[k], vv[k], dt, bad);
+    if (flops > 0) {
+        double a = xv[0];
+        for (int f = 0; f < flops / 2; ++f) a = __dadd_rn(__dmul_rn(a, 0.5), 0.25);
+        if (a < -1.0) bad |= PIC_DEV_RANGE;
+    }
+    if (!KEY) return 0u;
+    Axis ax[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
+    return bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
+}
+
+// How the fused step moves a particle: the leapfrog push of the PIC step, or
+// free streaming with periodic or reflecting walls (the particle-handling
+// benchmark, no field).
+constexpr int MOVE_PUSH = 0, MOVE_STREAM_PERIODIC = 1, MOVE_STREAM_REFLECTING = 2;
+static_assert(MOVE_STREAM_PERIODIC - 1 == PIC_PERIODIC && MOVE_STREAM_REFLECTING - 1 == PIC_REFLECTING,
+              "a streaming move's wall rule is MOVE - 1");
+
 // Key of one particle of the fused step: pushes it (push_one, so the same
 // state and bin as every other pass) and returns 2 * new bin + arrived.  A
 // particle stays iff its slot lies in its new bin's old segment.  When the
@@ -370,12 +426,12 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
 // its bin and segment come from scalar loads.  Other lanes load the new bin's
 // segment.  Call with every lane of the wavefront that holds a particle.
 // xv, vv: the particle's state, loaded by the caller (and pushed here).
-template <int D, int SCHEME, bool REG, bool MULTI>
+template <int D, int SCHEME, bool REG, bool MULTI, int MOVE = MOVE_PUSH>
 __device__ __forceinline__ uint32_t step_key_one(const DevTree &t, const DevInst &in0, const F64Ptrs &P, int64_t p,
                                                  double (&xv)[D], double (&vv)[D], double qmdt0, double dt0,
                                                  const double *qa, const double *da, const int64_t *inst_start,
                                                  const int64_t *old_start, uint32_t n_bins, const int32_t *lds,
-                                                 int lds_n, uint32_t &bad) {
+                                                 int lds_n, uint32_t &bad, int flops = 0) {
     int ii = 0;
     if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
     const DevInst &in = MULTI ? t.inst[ii] : in0;
@@ -392,7 +448,11 @@ __device__ __forceinline__ uint32_t step_key_one(const DevTree &t, const DevInst
             m = __umul24(m, (uint32_t)in.S);
         }
     }
-    uint32_t b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
+    uint32_t b;
+    if constexpr (MOVE == MOVE_PUSH)
+        b = push_one<D, SCHEME, REG, false>(t, in, P, lds, lds_n, xv, vv, qmdt, dt, p, bad);
+    else
+        b = stream_one<D, SCHEME, REG, MOVE - 1, true>(t, in, lds, lds_n, xv, vv, dt, flops, bad);
     if (b >= n_bins) bad |= PIC_DEV_RANGE;
     b = min(b, n_bins - 1);
     bool stay = false, known = !old_start;

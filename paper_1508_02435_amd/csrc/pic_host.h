@@ -159,6 +159,9 @@ hipError_t launch_stream_push(int dim, int64_t n, double *const *x, double *cons
 hipError_t launch_free_stream(const pic_tree *t, int scheme, pic_particles *p, double dt, const double *dt_dev,
                               int boundary, int flops, uint32_t *bin, hipStream_t s);
 hipError_t launch_leaf_counts(const pic_tree *t, const pic_particles *p, unsigned long long *count, hipStream_t s);
+hipError_t launch_stream_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start, double dt,
+                              int boundary, int flops, const Cols &extra, pic_particles *out, int64_t *new_start,
+                              void *scratch, size_t scratch_bytes, void *stats, hipStream_t s);
 pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc, int max_level,
                        std::vector<uint8_t> &masks, int &new_L);
 hipError_t launch_vmax(const pic_tree *t, int scheme, const pic_particles *p, const int64_t *bin_start, double dt,

@@ -11,33 +11,6 @@
 
 namespace pic {
 
-// One axis of a free-streaming move: x + v dt, then the wall rule.  Periodic:
-// x - floor(x), 1 -> 0 (the push's wrap).  Reflecting: mirrored at 0 (x ->
-// -x) or at 1 (x -> 2 - x, exact for x in [1, 2)), with the velocity
-// component negated; a landing exactly on 1 goes to the largest double below
-// 1.  A move that one mirror cannot bring back into the box is flagged and
-// clamped (the bin stays in range).
-template <int BC>
-__device__ __forceinline__ void stream_axis(double &x, double &v, double dt, uint32_t &bad) {
-    double y = __dadd_rn(x, __dmul_rn(v, dt));
-    if (BC == PIC_PERIODIC) {
-        y = __dsub_rn(y, floor(y));
-        if (y == 1.0) y = 0.0;
-    } else if (y < 0.0) {
-        y = -y;
-        v = -v;
-    } else if (y >= 1.0) {
-        y = __dsub_rn(2.0, y);
-        v = -v;
-        if (y == 1.0) y = 0x1.fffffffffffffp-1;
-    }
-    if (!(y >= 0.0 && y < 1.0)) {
-        bad |= (y - y == 0.0) ? PIC_DEV_RANGE : PIC_DEV_NONFINITE;
-        y = (y >= 1.0) ? 0x1.fffffffffffffp-1 : 0.0;
-    }
-    x = y;
-}
-
 template <int D, int SCHEME, bool REG, bool MULTI, int BC>
 __global__ __launch_bounds__(256) void k_free_stream(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double dt0,
                                                      const double *dt_arr, const int64_t *inst_start, int flops,
@@ -57,22 +30,13 @@ __global__ __launch_bounds__(256) void k_free_stream(DevTree t, DevInst in0, F64
             xv[k] = P.x[k][p];
             vv[k] = P.v[k][p];
         }
-#pragma unroll
-        for (int k = 0; k < D; ++k) stream_axis<BC>(xv[k], vv[k], dt, bad);
-        // the artificial flops: a dependent chain of multiplies and adds
-        // whose result only feeds a test that never holds
-        double a = xv[0];
-        for (int f = 0; f < flops / 2; ++f) a = __dadd_rn(__dmul_rn(a, 0.5), 0.25);
-        if (a < -1.0) bad |= PIC_DEV_RANGE;
+        const uint32_t b = stream_one<D, SCHEME, REG, BC, true>(t, in, lds, lds_n, xv, vv, dt, flops, bad);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             P.x[k][p] = xv[k];
             P.v[k][p] = vv[k];
         }
-        Axis ax[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) ax[k] = scale_axis(xv[k], in.Sd, in.S, bad);
-        bin_out[p] = bin_of<D, SCHEME, REG>(t, in, ax, lds, lds_n);
+        bin_out[p] = b;
         if (bad) flag_status(t.status, bad);
     }
 }

@@ -15,12 +15,12 @@ namespace pic {
 // 2*bin + arrived written out; with `store` the pushed state also goes back
 // to the input arrays, in place, so that the writing pass only moves it.
 // It also clears the per-call counters.
-template <int D, int SCHEME, bool REG, bool MULTI>
+template <int D, int SCHEME, bool REG, bool MULTI, int MOVE>
 __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const int64_t *old_start,
                                                   uint32_t n_bins, uint32_t *key_out, uint32_t *zero,
-                                                  int64_t n_zero, int store) {
+                                                  int64_t n_zero, int store, int flops) {
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
     const int lds_n = MULTI ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -33,8 +33,8 @@ __global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptr
             xv[k] = P.x[k][p];
             vv[k] = P.v[k][p];
         }
-        key_out[p] = step_key_one<D, SCHEME, REG, MULTI>(t, in0, P, p, xv, vv, qmdt0, dt0, qa, da, inst_start,
-                                                         old_start, n_bins, lds, lds_n, bad);
+        key_out[p] = step_key_one<D, SCHEME, REG, MULTI, MOVE>(t, in0, P, p, xv, vv, qmdt0, dt0, qa, da,
+                                                               inst_start, old_start, n_bins, lds, lds_n, bad, flops);
         if (store) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void emit_edges(const double (*s_edge)[2][NSD], const
 // wavefront; the wavefront it started in adds the later pieces in wavefront
 // order.  No float atomics: every sum has a fixed order.  k_deposit_runs
 // then adds each bin's runs in output order.
-template <int D, int SCHEME, bool REG, bool MULTI, int TILE, int NT, bool DEP>
+template <int D, int SCHEME, bool REG, bool MULTI, int TILE, int NT, bool DEP, int MOVE>
 __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const uint32_t *meta,
@@ -301,7 +301,10 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         const DevInst &in = MULTI ? t.inst[ii] : in0;
         const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
         const double dt = (MULTI && da) ? da[ii] : dt0;
-        push_one<D, SCHEME, REG, false, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
+        if constexpr (MOVE == MOVE_PUSH)
+            push_one<D, SCHEME, REG, false, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
+        else   // the artificial flops belong to the key pass's move only
+            stream_one<D, SCHEME, REG, MOVE - 1, false>(t, in, lds, lds_n, xv[j], vv[j], dt, 0, bad);
     }
     if (miss) flag_status(t.status, PIC_DEV_RANGE);
 #pragma unroll
@@ -404,36 +407,41 @@ struct StepArgs {
     uint32_t n_bins;
     void *stats;      // nullable pic_rebin_stats record
     bool deposit;     // the writing pass deposits (2D regular single trees, uniform charge)
+    int flops;        // free streaming: artificial flops per move (key pass)
 };
 
 #define PIC_EMIT(NT, DEP)                                                                                     \
-    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP>), dim3(tiles), dim3(NT), 0, s, t->dt,  \
+    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP, MOVE>), dim3(tiles), dim3(NT), 0, s,    \
+               t->dt,                                                                                               \
                t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,          \
                (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, (const uint32_t *)sc.run_pos,      \
                sc.run_part, a.out, extra, t->tune.xcd_tiles, stored ? 1 : 0)
 
-template <int D, int SCH, bool REG, bool MULTI, int TILE>
+template <int D, int SCH, bool REG, bool MULTI, int TILE, int MOVE = MOVE_PUSH>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + TILE - 1) / TILE;
-    // the key pass stores the pushed state (the fused key+rank kernel does not)
-    const bool stored = t->tune.key_stores == 1 && !t->tune.step_fuse;
-    if (a.n > 0 && t->tune.step_fuse) {
+    // the fused key+rank kernel pushes only; a streaming step takes the key
+    // and ranking passes
+    const bool fuse = t->tune.step_fuse && MOVE == MOVE_PUSH;
+    // the key pass stores the moved state (the fused key+rank kernel does not)
+    const bool stored = t->tune.key_stores == 1 && !fuse;
+    if (a.n > 0 && fuse) {
         // counters cleared first; the key pass and the ranking are one kernel
         launch_prep(a.zero, a.n_zero, nullptr, a.n_bins, a.n, TILE, sc, s);
         launch_keyrank(t, SCH, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins, TILE, sc,
                        a.stats ? sc.keys : nullptr, s);
         if (a.stats) (void)launch_rebin_stats(t, SCH, a.old_start, sc.keys, 1, a.n, a.stats, s);
     } else if (a.n > 0) {
-        PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0, s,
-                   t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
-                   sc.keys, a.zero, a.n_zero, stored ? 1 : 0);
+        PIC_LAUNCH("step_key", (k_step_key<D, SCH, REG, MULTI, MOVE>), dim3(grid_for(a.n, 256, 1 << 20)), dim3(256), 0,
+                   s, t->dt, t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, a.old_start, a.n_bins,
+                   sc.keys, a.zero, a.n_zero, stored ? 1 : 0, a.flops);
         if (a.stats) (void)launch_rebin_stats(t, SCH, a.old_start, sc.keys, 1, a.n, a.stats, s);
         launch_group(sc.keys, a.n, TILE, t->tune.group_match != 0, sc, s);
     }
     launch_step_middle(t, a.n, a.n_bins, sc, new_start, s);
     if (a.n == 0) return;
-    if constexpr (D == 2 && REG && !MULTI) {
+    if constexpr (D == 2 && REG && !MULTI && MOVE == MOVE_PUSH) {
         if (a.deposit) {
             if (t->tune.emit_threads == 512) PIC_EMIT(512, true);
             else PIC_EMIT(1024, true);
@@ -493,6 +501,7 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     a.n_bins = (uint32_t)n_bins;
     a.stats = stats;
     a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && t->tune.emit_deposit;
+    a.flops = 0;
     if (t->dim == 2) {
         if (scheme == PIC_PIT) launch_step_shape<2, 0>(t, a, sc, extra, new_start, s);
         else launch_step_shape<2, 1>(t, a, sc, extra, new_start, s);
@@ -510,6 +519,69 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     else PIC_LAUNCH("deposit_runs", k_deposit_runs<9>, g, b, 0, s, (const uint32_t *)sc.list_off, n_bins,
                     (const double *)sc.run_part, partial);
     launch_deposit_vertices(t, scheme, true, partial, false, q_uniform, rho, s);
+    return hipGetLastError();
+}
+
+// The fused form of the particle-handling benchmark's step (single trees):
+// the key pass streams every particle (with the artificial flops) and keys
+// it, the ranking, scan and placement as in pic_step, the writing pass
+// streams it again without the flops; no deposit.
+template <int D, int SCH, int MOVE>
+static void launch_stream_shape(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
+                                int64_t *new_start, hipStream_t s) {
+    const bool reg = t->reg_kernels != 0, small = t->tune.step_ipt == 4;
+    if (reg) {
+        if (small) launch_step_passes<D, SCH, true, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        else launch_step_passes<D, SCH, true, false, 2048, MOVE>(t, a, sc, extra, new_start, s);
+    } else {
+        if (small) launch_step_passes<D, SCH, false, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        else launch_step_passes<D, SCH, false, false, 2048, MOVE>(t, a, sc, extra, new_start, s);
+    }
+}
+
+template <int D, int SCH>
+static void launch_stream_bc(const pic_tree *t, int boundary, const StepArgs &a, const RebinScratch &sc,
+                             const Cols &extra, int64_t *new_start, hipStream_t s) {
+    if (boundary == PIC_PERIODIC) launch_stream_shape<D, SCH, MOVE_STREAM_PERIODIC>(t, a, sc, extra, new_start, s);
+    else launch_stream_shape<D, SCH, MOVE_STREAM_REFLECTING>(t, a, sc, extra, new_start, s);
+}
+
+hipError_t launch_stream_step(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start, double dt,
+                              int boundary, int flops, const Cols &extra, pic_particles *out, int64_t *new_start,
+                              void *scratch, size_t scratch_bytes, void *stats, hipStream_t s) {
+    const int64_t n = in->n;
+    const int64_t n_bins = n_bins_of(t, scheme);
+    const int tile = RB_THREADS * t->tune.step_ipt;
+    const int ns = scheme == PIC_PIT ? 4 : 9;
+    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 ? ns : 0);   // the layout pic_step uses
+    if (scratch_bytes < L.total) return hipErrorInvalidValue;
+    char *base = (char *)scratch;
+    const RebinScratch sc = bind_scratch(L, base);
+    const int64_t zero_words = (int64_t)((L.key_base - L.key_cn) / 4);
+    StepArgs a;
+    a.zero = (uint32_t *)(base + L.key_cn);
+    a.n_zero = zero_words;
+    if (n == 0) launch_prep(a.zero, zero_words, nullptr, n_bins, n, tile, sc, s);
+    a.P = make_ptrs(t, in, nullptr, nullptr);
+    a.out = make_ptrs(t, out, nullptr, nullptr);
+    a.n = n;
+    a.qmdt = 0.0;
+    a.dt = dt;
+    a.qa = nullptr;
+    a.da = nullptr;
+    a.inst_start = in->inst_start_dev;
+    a.old_start = old_start;
+    a.n_bins = (uint32_t)n_bins;
+    a.stats = stats;
+    a.deposit = false;
+    a.flops = flops;
+    if (t->dim == 2) {
+        if (scheme == PIC_PIT) launch_stream_bc<2, 0>(t, boundary, a, sc, extra, new_start, s);
+        else launch_stream_bc<2, 1>(t, boundary, a, sc, extra, new_start, s);
+    } else {
+        if (scheme == PIC_PIT) launch_stream_bc<3, 0>(t, boundary, a, sc, extra, new_start, s);
+        else launch_stream_bc<3, 1>(t, boundary, a, sc, extra, new_start, s);
+    }
     return hipGetLastError();
 }
 

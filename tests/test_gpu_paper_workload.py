@@ -112,8 +112,9 @@ def _oracle_run(spec, scheme, x, v, steps, dt, boundary, ppc, cap, flops):
     return rec
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("dim,box,scheme", [(2, 0.1, 0), (2, 0.1, 1), (2, 1.0, 0), (3, 0.1, 0), (3, 0.1, 1)])
-def test_adaptive_runs_match_oracle(dim, box, scheme):
+def test_adaptive_runs_match_oracle(dim, box, scheme, fused):
     """Sub-box or homogeneous start, reflecting walls, ppc-driven tree: every
     step's state, order, offsets, lift statistics and tree equal the
     oracle's."""
@@ -133,7 +134,7 @@ def test_adaptive_runs_match_oracle(dim, box, scheme):
     changes = 0
     for k in range(steps):
         s = pic.new_stats(dev)
-        run.step_free(dt, pic._capi.REFLECTING, 128, stats=s)
+        (run.step_free_fused if fused else run.step_free)(dt, pic._capi.REFLECTING, 128, stats=s)
         got_stats = pic.read_stats(s)
         changes += run.adapt(ppc, cap)
         w = want[k]
@@ -167,3 +168,39 @@ def test_vmax_matches_oracle(name, scheme):
         assert np.array_equal(got.cpu().numpy(), np.concatenate(want))
         assert np.array_equal(quiet.cpu().numpy(), np.concatenate(wq))
     assert run.tree.status_sync() == 0
+
+
+@pytest.mark.parametrize("tile", [2048, 1024])
+@pytest.mark.parametrize("flops", [0, 64])
+@pytest.mark.parametrize("boundary", [pic._capi.PERIODIC, pic._capi.REFLECTING])
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("name", sorted(TREES))
+def test_stream_step_matches_oracle(name, scheme, boundary, flops, tile):
+    """pic_stream_step (free streaming in the passes of the fused step) against
+    the oracle's free streaming and stable re-bin: state, order, offsets and
+    statistics bit for bit, over three steps of uneven length (ragged last
+    tiles, particles several cells away)."""
+    dev = _dev()
+    spec = TREES[name]()
+    o = oracle.OracleTree(spec)
+    t = pic.Tree(spec).upload()
+    pic.tune("step_tile", tile, t)
+    rng = np.random.default_rng(len(name) + 10 * scheme + 3 * boundary)
+    n = 3 * 2048 + 517
+    x, v = _paper_particles(rng, spec.dim, n)
+    run = pic.FreeStreamRun(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+    run.initial_sort()
+    xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+    for dt in (0.01, 0.2, 0.05):
+        st = pic.new_stats(dev)
+        run.step_free_fused(dt, boundary, flops, stats=st)
+        x1, v1, nb = o.free_stream(xs, vs, dt, boundary, flops, scheme)
+        want = o.rebin_stats(start, nb, scheme)
+        perm, start = oracle.rebin(nb, o.n_bins(scheme), start)
+        xs, vs, ids = x1[:, perm], v1[:, perm], ids[perm]
+        torch.cuda.synchronize()
+        assert np.array_equal(run.start.cpu().numpy(), start)
+        assert np.array_equal(run.ids.cpu().numpy(), ids)
+        assert np.array_equal(run.x.cpu().numpy(), xs) and np.array_equal(run.v.cpu().numpy(), vs)
+        assert pic.read_stats(st) == want
+    assert t.status_sync() == 0
