@@ -413,6 +413,8 @@ pic_status pic_profile_only(const char *name);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
  *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
  *   "deposit_bpw"   bins such a lane group takes one after the other, 1 or 2 (default 1);
+ *   "deposit_batch" particles a bin's lane group takes per round in the FP64
+ *                   deposit, 64 or 256 (default 64; the FP32 deposit takes 256);
  *   "step_tile"     particles per tile of pic_step's ranking and writing passes,
  *                   1024 or 2048 (default 2048);
  *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's

@@ -275,6 +275,9 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
     } else if (k == "deposit_bpw") {
         if (!one_of({1, 2})) return false;
         g.deposit_bpw = (int)value;
+    } else if (k == "deposit_batch") {
+        if (!one_of({64, 256})) return false;
+        g.deposit_batch = (int)value;
     } else if (k == "emit_threads") {
         if (!one_of({512, 1024})) return false;
         g.emit_threads = (int)value;
@@ -314,6 +317,7 @@ int64_t tune_get(const Tuning &g, const char *name) {
     if (k == "group_match") return g.group_match;
     if (k == "key_stores") return g.key_stores;
     if (k == "deposit_bpw") return g.deposit_bpw;
+    if (k == "deposit_batch") return g.deposit_batch;
     return -1;
 }
 

@@ -55,6 +55,7 @@ struct Tuning {
     int group_match = 0;    // fused step's ranking pass: 1 = by wavefront key matching, 0 = by LDS tags and masks
     int emit_deposit = 0;   // fused step, 2D regular single trees, uniform charge: 1 = the writing pass deposits
     int deposit_bpw = 1;    // bins a deposit lane group takes one after the other: 1 or 2
+    int deposit_batch = 64; // particles a deposit lane group takes per round: 64 or 256
     int regular_tables = 1; // build Peano rank tables for regular instances (read when a tree is created)
 };
 extern Tuning g_tune;      // process defaults for trees created afterwards

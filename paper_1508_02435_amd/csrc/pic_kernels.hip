@@ -336,7 +336,11 @@ size_t deposit_scratch_bytes(const pic_tree *t, int scheme) {
 
 #define PIC_DEP_BINS(D, SCH, REG, G)                                                                          \
     do {                                                                                                      \
-        if (t->tune.deposit_bpw == 2)                                                                          \
+        if (small_batch)                                                                                       \
+            PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 64 / G, 1>),                            \
+                       dim3(grid_for(n_bins, 256 / G, 1 << 18)), dim3(256), 0, s, t->dt, t->inst0, P, p->n,   \
+                       bin_start, n_bins, q, partial);                                                        \
+        else if (t->tune.deposit_bpw == 2)                                                                     \
             PIC_LAUNCH("deposit_bins", (k_deposit_bins<D, SCH, REG, G, 256 / G, 2>),                          \
                        dim3(grid_for((n_bins + 1) / 2, 256 / G, 1 << 18)), dim3(256), 0, s, t->dt, t->inst0, P, p->n, \
                        bin_start, n_bins, q, partial);                                                        \
@@ -381,6 +385,9 @@ hipError_t launch_deposit(const pic_tree *t, int scheme, const pic_particles *p,
     double *partial = (double *)scratch;
     F64Ptrs P = make_ptrs(t, p, nullptr, nullptr);
     const bool reg = t->reg_kernels != 0;
+    // particles a bin's lane group takes per round: 64 (fewer registers, the
+    // default) or 256 (more loads in flight for large bins)
+    const bool small_batch = t->tune.deposit_batch == 64;
     if (t->dim == 2) {
         if (scheme == PIC_PIT) { if (reg) PIC_DISPATCH_DEP(2, 0, true); else PIC_DISPATCH_DEP(2, 0, false); }
         else { if (reg) PIC_DISPATCH_DEP(2, 1, true); else PIC_DISPATCH_DEP(2, 1, false); }

@@ -249,7 +249,8 @@ def test_forest_locate_and_step_match_oracle_per_instance():
 
 KNOB_SETS = ([dict(rebin_tile=t, rebin_radix=r, scatter_mode=m, scatter_nt=nt)
               for t in (2048, 4096) for r in (4, 5) for m in (0, 1) for nt in (0, 1)]
-             + [dict(scatter_group=g, deposit_lanes=d) for g in (1, 2, 4) for d in (16, 32, 64)])
+             + [dict(scatter_group=g, deposit_lanes=d) for g in (1, 2, 4) for d in (16, 32, 64)]
+             + [dict(deposit_batch=b, deposit_lanes=d) for b in (64, 256) for d in (16, 32, 64)])
 
 
 @pytest.mark.parametrize("knobs", KNOB_SETS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
