@@ -293,7 +293,13 @@ def run_batched(args, scheme):
     results = {}
 
     def timed_graph(st, label):
-        knobs = autotune.autotune(st, E, 0.0, 0.0, fused=True, steps=2, **kw)
+        if args.knob:   # the given launch shape instead of the autotuned one
+            for kv in args.knob:
+                name, value = kv.split("=")
+                pic.tune(name, int(value), t)
+            knobs = pic.tuning(t)
+        else:
+            knobs = autotune.autotune(st, E, 0.0, 0.0, fused=True, steps=2, **kw)
         g = pic.StepGraph(st, E, 0.0, 0.0, **kw)
         for _ in range(max(1, args.warmup // 2)):
             g.replay()

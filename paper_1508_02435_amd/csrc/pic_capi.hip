@@ -264,7 +264,7 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
         if (!one_of({0, 1})) return false;
         g.regular_tables = (int)value;
     } else if (k == "step_tile") {
-        if (!one_of({1024, 2048})) return false;
+        if (!one_of({0, 1024, 2048, 4096})) return false;
         g.step_ipt = (int)(value / 256);
     } else if (k == "scatter_nt") {
         if (!one_of({0, 1})) return false;

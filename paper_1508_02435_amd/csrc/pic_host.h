@@ -46,7 +46,8 @@ struct Tuning {
     int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
     int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
     int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
-    int step_ipt = 8;       // particles per thread in a fused-step tile: 4 (1024 tile) or 8 (2048 tile)
+    int step_ipt = 0;       // particles per thread in a fused-step tile: 4, 8 or 16 (1024, 2048, 4096 tile);
+                            // 0 = by dimension (step_ipt_of)
     int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
     int emit_threads = 1024; // threads per emit block: 512 or 1024
     int step_fuse = 0;      // fused step: 1 = key pass and tile ranking in one kernel, 0 = two kernels
@@ -83,6 +84,22 @@ struct pic_tree {
     pic::DevInst inst0{};              // instance 0 (passed by value for single trees)
     pic::Tuning tune{};                // launch-shape knobs of this tree
 };
+
+namespace pic {
+
+// Particles per thread of the fused step's tiles.  By default 3D trees with
+// at most 256 particles per bin on average take 4096-particle tiles: the
+// movers of a bin scatter over its 26 neighbours, so with few particles per
+// bin the (tile, key) runs are short, and a longer tile holds more of a bin's
+// sources (fewer, longer runs: fewer partly written cache lines in the
+// writing pass).  Fuller bins already give long runs and every other tree
+// takes 2048, which keeps more blocks resident.
+inline int step_ipt_of(const pic_tree *t, int64_t n, int64_t n_bins) {
+    if (t->tune.step_ipt) return t->tune.step_ipt;
+    return t->dim == 3 && n <= 256 * n_bins ? 16 : 8;
+}
+
+}  // namespace pic
 
 namespace pic {
 

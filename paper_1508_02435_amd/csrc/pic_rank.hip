@@ -640,11 +640,16 @@ void launch_group(const uint32_t *keys, int64_t n, int tile, bool match, const R
         if (tile == 1024)
             PIC_LAUNCH("step_group", (k_step_group_match<4>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta,
                        0);
+        else if (tile == 4096)
+            PIC_LAUNCH("step_group", (k_step_group_match<16>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc,
+                       sc.meta, 0);
         else
             PIC_LAUNCH("step_group", (k_step_group_match<8>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta,
                        0);
     } else if (tile == 1024) {
         PIC_LAUNCH("step_group", (k_step_group<4>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta, 0);
+    } else if (tile == 4096) {
+        PIC_LAUNCH("step_group", (k_step_group<16>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta, 0);
     } else {
         PIC_LAUNCH("step_group", (k_step_group<8>), dim3(tiles), dim3(RB_THREADS), 0, s, keys, n, sc, sc.meta, 0);
     }

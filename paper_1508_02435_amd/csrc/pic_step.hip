@@ -229,7 +229,10 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     constexpr int NSD = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
     static_assert(!DEP || (D == 2 && REG && !MULTI), "the writing pass deposits for 2D regular single trees");
     __shared__ int32_t lds[REG ? 1 : PIC_LDS_NODES];
-    __shared__ uint64_t s_val[2][TILE];
+    // columns staged per barrier pair: two, one for 4096-particle tiles (LDS)
+    constexpr int SC = TILE > 2048 ? 1 : 2;
+    static_assert(!DEP || SC == 2, "the writing-pass deposit needs both position columns staged at once");
+    __shared__ uint64_t s_val[SC][TILE];
     __shared__ uint32_t s_dst[TILE];
     __shared__ uint32_t s_rd[RUN_HEAD], s_ro[RUN_HEAD];
     __shared__ uint16_t s_rid[DEP ? TILE : 1];
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     // constants), then the extra columns, two at a time
     auto write_out = [&](int c0, int ncol) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < SC; ++g) {
             const int c = c0 + g;
             if (c >= ncol) break;
             const bool st = c < 2 * D;
@@ -335,9 +338,9 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         }
     };
 #pragma unroll
-    for (int c0 = 0; c0 < 2 * D; c0 += 2) {
+    for (int c0 = 0; c0 < 2 * D; c0 += SC) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < SC; ++g) {
             const int c = c0 + g;
 #pragma unroll
             for (int j = 0; j < IPT; ++j)
@@ -355,9 +358,9 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         __syncthreads();
     }
     const int ncol = 2 * D + extra.n;
-    for (int c0 = 2 * D; c0 < ncol; c0 += 2) {
+    for (int c0 = 2 * D; c0 < ncol; c0 += SC) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < SC; ++g) {
             const int c = c0 + g;
             if (c >= ncol) break;
             const int e = c - 2 * D;
@@ -408,6 +411,7 @@ struct StepArgs {
     void *stats;      // nullable pic_rebin_stats record
     bool deposit;     // the writing pass deposits (2D regular single trees, uniform charge)
     int flops;        // free streaming: artificial flops per move (key pass)
+    int ipt;          // particles per thread of a tile (step_ipt_of)
 };
 
 #define PIC_EMIT(NT, DEP)                                                                                     \
@@ -423,7 +427,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
     const int64_t tiles = (a.n + TILE - 1) / TILE;
     // the fused key+rank kernel pushes only; a streaming step takes the key
     // and ranking passes
-    const bool fuse = t->tune.step_fuse && MOVE == MOVE_PUSH;
+    const bool fuse = t->tune.step_fuse && MOVE == MOVE_PUSH && TILE <= 2048;
     // the key pass stores the moved state (the fused key+rank kernel does not)
     const bool stored = t->tune.key_stores == 1 && !fuse;
     if (a.n > 0 && fuse) {
@@ -441,7 +445,7 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
     }
     launch_step_middle(t, a.n, a.n_bins, sc, new_start, s);
     if (a.n == 0) return;
-    if constexpr (D == 2 && REG && !MULTI && MOVE == MOVE_PUSH) {
+    if constexpr (D == 2 && REG && !MULTI && MOVE == MOVE_PUSH && TILE <= 2048) {
         if (a.deposit) {
             if (t->tune.emit_threads == 512) PIC_EMIT(512, true);
             else PIC_EMIT(1024, true);
@@ -455,10 +459,12 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
 template <int D, int SCH>
 static void launch_step_shape(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                               int64_t *new_start, hipStream_t s) {
-    const bool multi = t->n_inst > 1, reg = t->reg_kernels != 0, small = t->tune.step_ipt == 4;
+    const bool multi = t->n_inst > 1, reg = t->reg_kernels != 0;
+    const int ipt = a.ipt;
 #define PIC_STEP_TILE(REG, MULTI)                                                                            \
     do {                                                                                                     \
-        if (small) launch_step_passes<D, SCH, REG, MULTI, 1024>(t, a, sc, extra, new_start, s);             \
+        if (ipt == 4) launch_step_passes<D, SCH, REG, MULTI, 1024>(t, a, sc, extra, new_start, s);          \
+        else if (ipt == 16) launch_step_passes<D, SCH, REG, MULTI, 4096>(t, a, sc, extra, new_start, s);    \
         else launch_step_passes<D, SCH, REG, MULTI, 2048>(t, a, sc, extra, new_start, s);                   \
     } while (0)
     if (multi) {
@@ -475,9 +481,9 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
                        void *scratch, size_t scratch_bytes, void *stats, hipStream_t s) {
     const int64_t n = in->n;
     const int64_t n_bins = n_bins_of(t, scheme);
-    const int tile = RB_THREADS * t->tune.step_ipt;
+    const int ipt = step_ipt_of(t, n, n_bins), tile = RB_THREADS * ipt;
     const int ns = scheme == PIC_PIT ? 4 : 9;   // 2D deposit slots per run
-    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 ? ns : 0);
+    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 && tile <= 2048 ? ns : 0);
     if (scratch_bytes < L.total || scratch_bytes < deposit_scratch_bytes(t, scheme)) return hipErrorInvalidValue;
     char *base = (char *)scratch;
     const RebinScratch sc = bind_scratch(L, base);
@@ -500,8 +506,9 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     a.old_start = old_start;
     a.n_bins = (uint32_t)n_bins;
     a.stats = stats;
-    a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && t->tune.emit_deposit;
+    a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && t->tune.emit_deposit && tile <= 2048;
     a.flops = 0;
+    a.ipt = ipt;
     if (t->dim == 2) {
         if (scheme == PIC_PIT) launch_step_shape<2, 0>(t, a, sc, extra, new_start, s);
         else launch_step_shape<2, 1>(t, a, sc, extra, new_start, s);
@@ -529,12 +536,15 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
 template <int D, int SCH, int MOVE>
 static void launch_stream_shape(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
                                 int64_t *new_start, hipStream_t s) {
-    const bool reg = t->reg_kernels != 0, small = t->tune.step_ipt == 4;
+    const bool reg = t->reg_kernels != 0;
+    const int ipt = a.ipt;
     if (reg) {
-        if (small) launch_step_passes<D, SCH, true, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        if (ipt == 4) launch_step_passes<D, SCH, true, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        else if (ipt == 16) launch_step_passes<D, SCH, true, false, 4096, MOVE>(t, a, sc, extra, new_start, s);
         else launch_step_passes<D, SCH, true, false, 2048, MOVE>(t, a, sc, extra, new_start, s);
     } else {
-        if (small) launch_step_passes<D, SCH, false, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        if (ipt == 4) launch_step_passes<D, SCH, false, false, 1024, MOVE>(t, a, sc, extra, new_start, s);
+        else if (ipt == 16) launch_step_passes<D, SCH, false, false, 4096, MOVE>(t, a, sc, extra, new_start, s);
         else launch_step_passes<D, SCH, false, false, 2048, MOVE>(t, a, sc, extra, new_start, s);
     }
 }
@@ -551,9 +561,9 @@ hipError_t launch_stream_step(const pic_tree *t, int scheme, pic_particles *in, 
                               void *scratch, size_t scratch_bytes, void *stats, hipStream_t s) {
     const int64_t n = in->n;
     const int64_t n_bins = n_bins_of(t, scheme);
-    const int tile = RB_THREADS * t->tune.step_ipt;
+    const int ipt = step_ipt_of(t, n, n_bins), tile = RB_THREADS * ipt;
     const int ns = scheme == PIC_PIT ? 4 : 9;
-    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 ? ns : 0);   // the layout pic_step uses
+    const RebinLayout L = rebin_layout(n, n_bins, tile, t->dim == 2 && tile <= 2048 ? ns : 0);   // as pic_step
     if (scratch_bytes < L.total) return hipErrorInvalidValue;
     char *base = (char *)scratch;
     const RebinScratch sc = bind_scratch(L, base);
@@ -575,6 +585,7 @@ hipError_t launch_stream_step(const pic_tree *t, int scheme, pic_particles *in, 
     a.stats = stats;
     a.deposit = false;
     a.flops = flops;
+    a.ipt = ipt;
     if (t->dim == 2) {
         if (scheme == PIC_PIT) launch_stream_bc<2, 0>(t, boundary, a, sc, extra, new_start, s);
         else launch_stream_bc<2, 1>(t, boundary, a, sc, extra, new_start, s);

@@ -84,12 +84,13 @@ class Forest:
                 assert (err <= RHO_TOL * np.abs(s["rho"]) + 1e-300).all(), f"charge of instance {i}"
 
 
-@pytest.mark.parametrize("key_stores", [0, 1])
+@pytest.mark.parametrize("key_stores,step_tile", [(0, 2048), (1, 2048), (0, 4096)])
 @pytest.mark.parametrize("scheme", [pic.PIT, pic.PIDT])
-def test_forest_fused_steps_match_oracle_per_instance(scheme, key_stores):
+def test_forest_fused_steps_match_oracle_per_instance(scheme, key_stores, step_tile):
     dev = _dev()
     f = Forest(dev, scheme)
     pic.tune("key_stores", key_stores, f.tree)
+    pic.tune("step_tile", step_tile, f.tree)
     st = pic.Stepper(f.tree, scheme, f.x, f.v, ids=f.ids, inst_start=f.inst_start, device=dev)
     st.initial_sort()
     torch.cuda.synchronize()

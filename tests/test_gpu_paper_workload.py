@@ -170,7 +170,7 @@ def test_vmax_matches_oracle(name, scheme):
     assert run.tree.status_sync() == 0
 
 
-@pytest.mark.parametrize("tile", [2048, 1024])
+@pytest.mark.parametrize("tile", [2048, 1024, 4096])
 @pytest.mark.parametrize("flops", [0, 64])
 @pytest.mark.parametrize("boundary", [pic._capi.PERIODIC, pic._capi.REFLECTING])
 @pytest.mark.parametrize("scheme", [0, 1])

@@ -318,6 +318,11 @@ STEP_FORMS = [dict(step_fuse=f, group_match=gm, emit_threads=nt, xcd_tiles=x, st
               for dep in (1, 0)]
 STEP_FORMS += [dict(step_fuse=0, group_match=0, emit_threads=nt, xcd_tiles=1, step_tile=tl, emit_deposit=dep,
                     key_stores=1) for nt in (1024, 512) for tl in (2048, 1024) for dep in (1, 0)]
+# 4096-particle tiles: one staged column at a time, whatever step_fuse and
+# emit_deposit say
+STEP_FORMS += [dict(step_fuse=f, group_match=gm, emit_threads=nt, xcd_tiles=x, step_tile=4096, emit_deposit=1,
+                    key_stores=ks) for f, gm in ((1, 0), (0, 0), (0, 1)) for nt in (1024, 512) for x in (1, 0)
+               for ks in (0, 1)]
 
 
 @pytest.mark.parametrize("knobs", STEP_FORMS, ids=lambda k: "-".join(f"{v}" for v in k.values()))
@@ -356,7 +361,7 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
 
 @pytest.mark.parametrize("tiles", [80, 160])
 @pytest.mark.parametrize("step_fuse,group_match", [(1, 0), (0, 1), (0, 0)])
-@pytest.mark.parametrize("step_tile", [2048, 1024])
+@pytest.mark.parametrize("step_tile", [2048, 1024, 4096])
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, group_match, scheme, tiles):
     """Every tile sends particles to every bin of a 3x3 tree, so each key
@@ -394,7 +399,8 @@ def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, group_match, s
 
 MANY_RUN_FORMS = [dict(), dict(emit_threads=512), dict(step_tile=1024), dict(step_tile=1024, emit_threads=512),
                   dict(step_fuse=1), dict(step_fuse=1, step_tile=1024), dict(group_match=1),
-                  dict(group_match=1, step_tile=1024)]
+                  dict(group_match=1, step_tile=1024), dict(step_tile=4096), dict(step_tile=4096, emit_threads=512),
+                  dict(step_tile=4096, group_match=1)]
 
 
 @pytest.mark.parametrize("knobs", MANY_RUN_FORMS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()) or "default")
@@ -409,7 +415,7 @@ def test_fused_step_with_many_runs_per_tile(scheme, knobs):
     try:
         for k, v in knobs.items():
             pic.tune(k, v)
-        tile = pic.tuning()["step_tile"]
+        tile = pic.tuning()["step_tile"] or 2048   # 0: by dimension, 2048 for 2D trees
         rng = np.random.default_rng(47)
         spec = W.regular_tree(2, 3)
         n = 5 * 2048 + 333
@@ -440,8 +446,8 @@ def test_fused_step_with_many_runs_per_tile(scheme, knobs):
 
 
 @pytest.mark.parametrize("spread", [0.05, 0.5])
-@pytest.mark.parametrize("step_tile", [2048, 1024])
-@pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 5 * 2048 + 3])
+@pytest.mark.parametrize("step_tile", [2048, 1024, 4096])
+@pytest.mark.parametrize("n", [1, 1023, 2047, 2048, 2049, 4097, 5 * 2048 + 3])
 def test_fused_and_separate_calls_agree_bitwise(n, step_tile, spread):
     """spread 0.5 scatters a tile over most of the tree's bins, so tiles hold
     far more distinct keys than the fast rank path takes."""
@@ -651,7 +657,7 @@ def test_fused_step_with_short_direct_run_lists(scheme, clusters, spread, most):
     xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
     # the case is the one meant: in the first step some key (a stayer key of
     # the sorted input) has more runs than the direct list holds
-    tile = pic.tuning()["step_tile"]
+    tile = pic.tuning()["step_tile"] or 2048   # 0: by dimension, 2048 for 2D trees
     old_bin = np.repeat(np.arange(len(start) - 1), np.diff(start))
     runs = {}
     for a in range(0, n, tile):
