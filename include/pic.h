@@ -416,9 +416,11 @@ pic_status pic_profile_only(const char *name);
  *   "deposit_batch" particles a bin's lane group takes per round in the FP64
  *                   deposit, 64 or 256 (default 64; the FP32 deposit takes 256);
  *   "step_tile"     particles per tile of pic_step's ranking and writing passes,
- *                   1024, 2048 or 4096, or 0 = 4096 for 3D trees and 2048 for 2D
- *                   ones (default 0; 4096-particle tiles stage one column at a
- *                   time and ignore step_fuse and emit_deposit);
+ *                   1024, 2048 or 4096, or 0 = 4096 for 3D trees with at most 256
+ *                   particles per bin on average and 2048 otherwise (default 0;
+ *                   4096-particle tiles stage one column at a time and ignore
+ *                   step_fuse and emit_deposit; the FP32 form takes 4096 where
+ *                   the FP64 form would, 2048 otherwise);
  *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's
  *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
  *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);

@@ -286,9 +286,11 @@ __device__ __forceinline__ uint32_t old_bin_wave(const int64_t *start, uint32_t 
 // FP32 form, key pass of pic_step: one particle per thread, pushed, its key
 // 2*bin + arrived written out (a particle arrives iff its bin changes: the
 // bin is implicit in the segment it is stored in); with `store` the pushed
-// offsets and velocities go back to the input arrays in place.
+// offsets and velocities go back to the input arrays in place.  Like the
+// FP64 key pass it waits on chained loads, so single trees ask for six
+// resident wavefronts per SIMD (72 registers in 3D).
 template <int D, int SCHEME, bool MULTI>
-__global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
+__global__ __launch_bounds__(256, MULTI ? 4 : 6) void k_step_key_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
                                                       double dt0, const double *qa, const double *da,
                                                       const int64_t *inst_start, const int64_t *bin_start,
                                                       uint32_t n_bins, const uint32_t *tile_bin, int tile,
@@ -326,17 +328,19 @@ __global__ __launch_bounds__(256) void k_step_key_f32(DevTree t, DevInst in0, F3
     }
 }
 
-// FP32 form, emit pass of pic_step: the state pushed again is staged through
-// LDS in tile-sorted order, one column at a time, and written run by run (as
-// k_step_emit).
-template <int D, int SCHEME, bool MULTI, int TILE, int NT>
+// FP32 form, emit pass of pic_step: the state pushed again (or, with
+// PUSHED, as the key pass stored it) is staged through LDS in tile-sorted
+// order, one column at a time, and written run by run (as k_step_emit).  The
+// moving-only form holds no push code, so it needs fewer registers and more
+// blocks fit a CU.
+template <int D, int SCHEME, bool MULTI, int TILE, int NT, bool PUSHED>
 __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F32Ptrs P, int64_t n, double qmdt0,
                                                       double dt0, const double *qa, const double *da,
                                                       const int64_t *inst_start, const int64_t *bin_start,
                                                       uint32_t n_bins, const uint32_t *tile_bin,
                                                       const uint32_t *meta, const uint32_t *run_dest,
                                                       const uint32_t *run_info, F32Ptrs out, Cols extra, int xcd,
-                                                      const uint32_t *wave_bin, int pushed) {
+                                                      const uint32_t *wave_bin) {
     constexpr int IPT = TILE / NT;
     __shared__ uint64_t s_val[TILE];
     __shared__ uint32_t s_dst[TILE];
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_step_emit_f32(DevTree t, DevInst in0, F3
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
-        if (pushed || p >= n) continue;   // pushed: the key pass stored the state
+        if (PUSHED || p >= n) continue;   // PUSHED: the key pass stored the state
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
         const DevInst &in = MULTI ? t.inst[ii] : in0;
@@ -681,20 +685,28 @@ template <int D, int SCH, bool MULTI>
 static void step_passes_f32(const pic_tree *t, const F32Ptrs &P, const F32Ptrs &Q, int64_t n, double qmdt, double dt,
                             const double *qa, const double *da, const int64_t *inst_start, const int64_t *old_start,
                             uint32_t n_bins, const RebinScratch &sc, const Cols &extra, int64_t *new_start,
-                            void *stats, hipStream_t s) {
-    constexpr int TILE = 2048;
-    const int64_t tiles = (n + TILE - 1) / TILE;
+                            void *stats, int tile, hipStream_t s) {
+    const int64_t tiles = (n + tile - 1) / tile;
     const int stored = t->tune.key_stores == 1 || (t->tune.key_stores == 2 && D == 3);
     PIC_LAUNCH("step_key_f32", (k_step_key_f32<D, SCH, MULTI>), dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
                t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
-               TILE, sc.keys, (const uint32_t *)sc.wave_bin, stored);
+               tile, sc.keys, (const uint32_t *)sc.wave_bin, stored);
     if (stats) (void)launch_rebin_stats(t, SCH, old_start, sc.keys, 1, n, stats, s);
-    launch_group(sc.keys, n, TILE, t->tune.group_match != 0, sc, s);
+    launch_group(sc.keys, n, tile, t->tune.group_match != 0, sc, s);
     launch_step_middle(t, n, n_bins, sc, new_start, s);
-    PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024>), dim3(tiles), dim3(1024), 0, s, t->dt,
-               t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins, (const uint32_t *)sc.tile_bin,
-               (const uint32_t *)sc.meta, (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, Q, extra,
-               t->tune.xcd_tiles, (const uint32_t *)sc.wave_bin, stored);
+#define PIC_EMIT_F32(TILE, PUSHED)                                                                                 \
+    PIC_LAUNCH("step_emit_f32", (k_step_emit_f32<D, SCH, MULTI, TILE, 1024, PUSHED>), dim3(tiles), dim3(1024), 0, s,  \
+               t->dt, t->inst0, P, n, qmdt, dt, qa, da, inst_start, old_start, n_bins,                              \
+               (const uint32_t *)sc.tile_bin, (const uint32_t *)sc.meta, (const uint32_t *)sc.run_dest,              \
+               (const uint32_t *)sc.run_info, Q, extra, t->tune.xcd_tiles, (const uint32_t *)sc.wave_bin)
+    if (tile == 4096) {
+        if (stored) PIC_EMIT_F32(4096, true);
+        else PIC_EMIT_F32(4096, false);
+    } else {
+        if (stored) PIC_EMIT_F32(2048, true);
+        else PIC_EMIT_F32(2048, false);
+    }
+#undef PIC_EMIT_F32
 }
 
 hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, const int64_t *old_start,
@@ -705,18 +717,19 @@ hipError_t launch_step_f32(const pic_tree *t, int scheme, pic_particles *in, con
     const int64_t n_bins = n_bins_of(t, scheme);
     if (scratch_bytes < step_f32_scratch_bytes(t, n, scheme)) return hipErrorInvalidValue;
     if (n > 0) {
-        // key, group, scan, place and emit passes, as the FP64 step
-        constexpr int TILE = 2048;
-        const RebinLayout L = rebin_layout(n, n_bins, TILE);
+        // key, group, scan, place and emit passes, as the FP64 step; tiles of
+        // 4096 where that step takes them (step_ipt_of), else 2048
+        const int tile = step_ipt_of(t, n, n_bins) == 16 ? 4096 : 2048;
+        const RebinLayout L = rebin_layout(n, n_bins, tile);
         char *base = (char *)scratch;
         const RebinScratch sc = bind_scratch(L, base);
         const int64_t zero_words = (int64_t)((L.key_base - L.key_cnt) / 4);
-        launch_prep((uint32_t *)(base + L.key_cnt), zero_words, old_start, n_bins, n, TILE, sc, s);
+        launch_prep((uint32_t *)(base + L.key_cnt), zero_words, old_start, n_bins, n, tile, sc, s);
         const F32Ptrs P = make_f32(t, in, E), Q = make_f32(t, out, E);
         const double *qa = pp ? pp->qmdt_dev : nullptr;
         const double *da = pp ? pp->dt_dev : nullptr;
         PIC_SWITCH_DSM(step_passes_f32, t, P, Q, n, qmdt, dt, qa, da, in->inst_start_dev, old_start,
-                       (uint32_t)n_bins, sc, extra, new_start, stats, s);
+                       (uint32_t)n_bins, sc, extra, new_start, stats, tile, s);
         const double *q = q_col >= 0 ? (const double *)extra.out[q_col] : nullptr;
         return launch_deposit_f32(t, scheme, out, new_start, q, q_uniform, rho, scratch, scratch_bytes, s);
     }

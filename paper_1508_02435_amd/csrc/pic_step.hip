@@ -14,9 +14,11 @@ namespace pic {
 // Key pass of the unfused form: one particle per thread, pushed, its key
 // 2*bin + arrived written out; with `store` the pushed state also goes back
 // to the input arrays, in place, so that the writing pass only moves it.
-// It also clears the per-call counters.
+// It also clears the per-call counters.  Its loads wait on one another
+// (old bin, field, rank tables), so it wants resident wavefronts: at least
+// five per SIMD, which holds the 3D forms to 72 registers (seven resident).
 template <int D, int SCHEME, bool REG, bool MULTI, int MOVE>
-__global__ __launch_bounds__(256) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
+__global__ __launch_bounds__(256, 5) void k_step_key(DevTree t, DevInst in0, F64Ptrs P, int64_t n, double qmdt0,
                                                   double dt0, const double *qa, const double *da,
                                                   const int64_t *inst_start, const int64_t *old_start,
                                                   uint32_t n_bins, uint32_t *key_out, uint32_t *zero,

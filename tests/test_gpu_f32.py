@@ -107,15 +107,17 @@ def test_f32_step_error_against_oracle(name, scheme):
     check_rho_f32(o, r["x"], r["q"], wl.q_uniform, rho32, rho64, name)
 
 
-@pytest.mark.parametrize("key_stores", [0, 1])
+@pytest.mark.parametrize("key_stores,step_tile", [(0, 0), (1, 0), (0, 2048), (1, 2048), (0, 4096), (1, 4096)])
 @pytest.mark.parametrize("name,scheme", CASES)
-def test_f32_fused_equals_three_calls(name, scheme, key_stores):
+def test_f32_fused_equals_three_calls(name, scheme, key_stores, step_tile):
     """The single call (pushing twice, or storing the pushed state in the key
-    pass) gives the three calls' state, order and charge bit for bit."""
+    pass; tiles of 2048 or 4096 particles) gives the three calls' state,
+    order and charge bit for bit."""
     dev = _dev()
     rng = np.random.default_rng(12)
     wl, o, t, xs, vs, qs, start, E = _setup(name, scheme, dev, rng)
     pic.tune("key_stores", key_stores, t)
+    pic.tune("step_tile", step_tile, t)
     Ed = torch.tensor(E, device=dev)
     outs = []
     for fused in (False, True):
