@@ -172,6 +172,11 @@ const char *pic_status_string(pic_status s);
  * inst_start_dev: for a forest, n_inst+1 int64 particle offsets: the
  * particles of instance i are [inst_start[i], inst_start[i+1]), in order.
  * NULL for a single tree.  Particles never change instance.
+ *
+ * For a set a call writes (the `out` of pic_step and pic_stream_step), n is
+ * the capacity of its arrays and must equal the input's n, since a step
+ * keeps every particle: any other value is rejected with PIC_E_ARG before
+ * anything is enqueued.
  */
 typedef struct {
     int64_t n;

@@ -437,15 +437,30 @@ __device__ __forceinline__ uint32_t step_key_one(const DevTree &t, const DevInst
     const DevInst &in = MULTI ? t.inst[ii] : in0;
     const double qmdt = (MULTI && qa) ? qa[ii] : qmdt0;
     const double dt = (MULTI && da) ? da[ii] : dt0;
-    // finest cell of the old position (PIT on a regular instance: its bin)
+    // lattice index of the old position's bin on a regular instance: its
+    // finest cell (PIT) or its nearest vertex on the shifted lattice (PIDT),
+    // as bin_of forms them (clamped: it is only a hint, checked below).  Not
+    // for 3D PIDT, where the registers it holds cost more than it saves.
+    constexpr bool HINT = REG && (SCHEME == PIC_PIT || D == 2);
     uint32_t cold = 0;
-    if (SCHEME == PIC_PIT && REG) {
+    if (HINT) {
+        const uint32_t S = (uint32_t)in.S;
         uint32_t m = 1;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double y = x_scaled(xv[k], in.Sd);
-            cold += __umul24(min((uint32_t)max(y, 0.0), (uint32_t)in.S - 1u), m);
-            m = __umul24(m, (uint32_t)in.S);
+            uint32_t c;
+            if (SCHEME == PIC_PIT) {
+                c = min((uint32_t)max(y, 0.0), S - 1u);
+            } else {
+                const uint32_t T = (uint32_t)fmin(fmax(floor(2.0 * y), 0.0), (double)(2u * S - 1u));
+                c = (T + 1u) >> 1;
+                if (c >= S) c -= S;
+                c += (S - 1u) >> 1;
+                if (c >= S) c -= S;
+            }
+            cold += __umul24(c, m);
+            m = __umul24(m, S);
         }
     }
     uint32_t b;
@@ -456,15 +471,16 @@ __device__ __forceinline__ uint32_t step_key_one(const DevTree &t, const DevInst
     if (b >= n_bins) bad |= PIC_DEV_RANGE;
     b = min(b, n_bins - 1);
     bool stay = false, known = !old_start;
-    if (SCHEME == PIC_PIT && REG && !MULTI && old_start) {
+    if (HINT && !MULTI && old_start) {
         uint64_t pend = __ballot(1);
+        const uint32_t off = (uint32_t)(SCHEME == PIC_PIT ? in.leaf_off : in.pidt_off);
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             if (!pend) break;
             const uint32_t cu = (uint32_t)__builtin_amdgcn_readlane((int)cold, __builtin_ctzll(pend));
             const bool mine = cold == cu;
             pend &= ~__ballot(mine);
-            const uint32_t ob = (uint32_t)in.leaf_off + ld_const(t.peano_tab, (uint32_t)in.ptab + cu);
+            const uint32_t ob = off + ld_const(t.peano_tab, (uint32_t)in.ptab + cu);
             const int64_t s0 = ld_const(old_start, ob), s1 = ld_const(old_start, ob + 1u);
             if (mine && s0 <= p && p < s1) {
                 stay = b == ob;

@@ -160,6 +160,26 @@ def test_tuning_knobs_accept_only_listed_values():
             pic.tune(k, v)
 
 
+def test_output_sets_must_hold_every_particle():
+    """The output set of a step states its capacity in n: one smaller (or
+    larger) than the input is rejected before anything is enqueued."""
+    t = pic.Tree(W.regular_tree(2, 2))
+    L = _capi.lib()
+    P, Q = _capi.Particles(), _capi.Particles()
+    P.n, Q.n = 100, 99
+    P.x[0], P.x[1], P.v[0], P.v[1] = 0x1000, 0x2000, 0x3000, 0x4000
+    Q.x[0], Q.x[1], Q.v[0], Q.v[1] = 0x5000, 0x6000, 0x7000, 0x8000
+    E = (C.c_void_p * 3)(0x9000, 0xa000, None)
+    ptr = C.c_void_p
+    need = pic.scratch_bytes(t, 100, pic.PIT)
+    for qn, want in ((99, _capi.PIC_E_ARG), (101, _capi.PIC_E_ARG), (100, _capi.PIC_E_STATE)):
+        Q.n = qn
+        assert L.pic_step(t.handle, 0, 0, C.byref(P), ptr(0xb000), E, 0.0, 0.0, None, 0, None, None, None, -1,
+                          0.0, C.byref(Q), ptr(0xc000), ptr(0xd000), ptr(0xe000), need, None, None) == want
+        assert L.pic_stream_step(t.handle, 0, C.byref(P), ptr(0xb000), 0.1, _capi.REFLECTING, 0, 0, None, None,
+                                 None, C.byref(Q), ptr(0xc000), ptr(0xe000), need, None, None) == want
+
+
 def test_knobs_are_per_tree():
     """A tree copies the process defaults when it is created; changing one
     tree's knobs changes neither the defaults nor another tree's."""
