@@ -413,8 +413,9 @@ __device__ __forceinline__ uint32_t stream_one(const DevTree &t, const DevInst &
 
 // How the fused step moves a particle: the leapfrog push of the PIC step, or
 // free streaming with periodic or reflecting walls (the particle-handling
-// benchmark, no field).
-constexpr int MOVE_PUSH = 0, MOVE_STREAM_PERIODIC = 1, MOVE_STREAM_REFLECTING = 2;
+// benchmark, no field).  MOVE_STORED is the writing pass's form when the key
+// pass has stored the moved state: it only moves records.
+constexpr int MOVE_PUSH = 0, MOVE_STREAM_PERIODIC = 1, MOVE_STREAM_REFLECTING = 2, MOVE_STORED = 3;
 static_assert(MOVE_STREAM_PERIODIC - 1 == PIC_PERIODIC && MOVE_STREAM_REFLECTING - 1 == PIC_REFLECTING,
               "a streaming move's wall rule is MOVE - 1");
 

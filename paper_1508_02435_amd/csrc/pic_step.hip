@@ -225,7 +225,8 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
                                                   const int64_t *inst_start, const uint32_t *meta,
                                                   const uint32_t *run_dest, const uint32_t *run_info,
                                                   const uint32_t *run_pos, double *run_part, F64Ptrs out,
-                                                  Cols extra, int xcd, int pushed) {
+                                                  Cols extra, int xcd) {
+    constexpr bool PUSHED = MOVE == MOVE_STORED;   // the key pass stored the moved state
     constexpr int IPT = TILE / NT;
     constexpr int NW = NT / 64;
     constexpr int NSD = SCHEME == PIC_PIT ? (1 << D) : (D == 2 ? 9 : 27);
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
     __shared__ uint32_t s_erid[DEP ? NW : 1][2];                // their run ids | VALID | CONT
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x, xcd) * TILE;
-    const int lds_n = (MULTI || pushed) ? 0 : stage_nodes<REG>(t, in0, lds);
+    const int lds_n = (MULTI || PUSHED) ? 0 : stage_nodes<REG>(t, in0, lds);
     const int64_t base = lo + (int64_t)w * 64 * IPT + lane;
     const int cnt = (int)min((int64_t)TILE, n - lo);
     for (int i = tid; i < TILE; i += NT) s_dst[i] = ~0u;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t p = base + 64 * j;
-        if (pushed || !(full || p < n)) continue;
+        if (PUSHED || !(full || p < n)) continue;
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
         const DevInst &in = MULTI ? t.inst[ii] : in0;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(NT) void k_step_emit(DevTree t, DevInst in0, F64Ptr
         const double dt = (MULTI && da) ? da[ii] : dt0;
         if constexpr (MOVE == MOVE_PUSH)
             push_one<D, SCHEME, REG, false, false>(t, in, P, lds, lds_n, xv[j], vv[j], qmdt, dt, p, bad);
-        else   // the artificial flops belong to the key pass's move only
+        else if constexpr (!PUSHED)   // the artificial flops belong to the key pass's move only
             stream_one<D, SCHEME, REG, MOVE - 1, false>(t, in, lds, lds_n, xv[j], vv[j], dt, 0, bad);
     }
     if (miss) flag_status(t.status, PIC_DEV_RANGE);
@@ -416,12 +417,18 @@ struct StepArgs {
     int ipt;          // particles per thread of a tile (step_ipt_of)
 };
 
-#define PIC_EMIT(NT, DEP)                                                                                     \
-    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP, MOVE>), dim3(tiles), dim3(NT), 0, s,    \
+#define PIC_EMIT_AS(NT, DEP, EMOVE)                                                                           \
+    PIC_LAUNCH("step_emit", (k_step_emit<D, SCH, REG, MULTI, TILE, NT, DEP, EMOVE>), dim3(tiles), dim3(NT), 0, s,   \
                t->dt,                                                                                               \
                t->inst0, a.P, a.n, a.qmdt, a.dt, a.qa, a.da, a.inst_start, (const uint32_t *)sc.meta,          \
                (const uint32_t *)sc.run_dest, (const uint32_t *)sc.run_info, (const uint32_t *)sc.run_pos,      \
-               sc.run_part, a.out, extra, t->tune.xcd_tiles, stored ? 1 : 0)
+               sc.run_part, a.out, extra, t->tune.xcd_tiles)
+// the writing pass moves again, or only moves records the key pass stored
+#define PIC_EMIT(NT, DEP)                                                                                     \
+    do {                                                                                                      \
+        if (stored) PIC_EMIT_AS(NT, DEP, MOVE_STORED);                                                        \
+        else PIC_EMIT_AS(NT, DEP, MOVE);                                                                      \
+    } while (0)
 
 template <int D, int SCH, bool REG, bool MULTI, int TILE, int MOVE = MOVE_PUSH>
 static void launch_step_passes(const pic_tree *t, const StepArgs &a, const RebinScratch &sc, const Cols &extra,
