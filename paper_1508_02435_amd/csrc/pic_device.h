@@ -52,6 +52,15 @@ __device__ __forceinline__ uint32_t ld_const(const uint32_t *p, uint32_t idx) {
 
 __device__ __forceinline__ double x_scaled(double x, double Sd) { return __dmul_rn(x, Sd); }
 
+// Scalar passes of the field gather.  PIT: two (a wavefront of one bin
+// covers one or two cells).  PIDT: one; a bin spans the 2^d cells around
+// its vertex, and further serial passes cost more than the per-lane gathers
+// they replace (measured on the 2D and 3D plasma).
+template <int D, int SCHEME>
+constexpr int field_passes() {
+    return SCHEME == PIC_PIT ? 2 : 1;
+}
+
 // Scaled coordinate of one axis.  y = fl(x * S) is the only rounding on the
 // way to the cell; T = floor(2y) resolves half cells (dual-cell faces).  The
 // clamp keeps indices in range for malformed input (which is flagged).
@@ -283,7 +292,7 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
         w[c] = wc;
     }
     // Field at the corners.  Particles are stored by bin, so the lanes of a
-    // wavefront mostly share one or two cells: up to two passes serve the
+    // wavefront mostly share a few cells: up to field_passes passes serve the
     // lanes whose cell is that of the first pending lane (the id of corner 0
     // names the cell) with scalar loads, and only the lanes left gather per
     // lane.  The values, and so the arithmetic, are the same either way.
@@ -292,7 +301,7 @@ __device__ __forceinline__ uint32_t push_one(const DevTree &t, const DevInst &in
     uint64_t pend = __ballot(1);
     const uint32_t lane = __lane_id();
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < field_passes<D, SCHEME>(); ++it) {
         if (!pend) break;
         const int l = __builtin_ctzll(pend);
         const uint32_t v0u = (uint32_t)__builtin_amdgcn_readlane((int)vid[0], l);

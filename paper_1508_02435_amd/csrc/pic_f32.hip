@@ -131,12 +131,12 @@ __device__ __forceinline__ uint32_t push_f32(const DevTree &t, const DevInst &in
         w[cc] = wc;
     }
     // corner field: scalar loads for the lanes sharing the first pending
-    // lane's cell (two passes), per-lane loads for the rest
+    // lane's cell (field_passes passes), per-lane loads for the rest
     float Ec[1 << D][D];
     uint64_t pend = __ballot(1);
     const uint32_t lane = __lane_id();
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < field_passes<D, SCHEME>(); ++it) {
         if (!pend) break;
         const int l = __builtin_ctzll(pend);
         const uint32_t v0u = (uint32_t)__builtin_amdgcn_readlane((int)vid[0], l);
