@@ -543,15 +543,24 @@ __device__ __forceinline__ void place_counted(const RebinScratch &sc, const uint
     }
 }
 
+#ifndef PIC_PLACE_KW
+#define PIC_PLACE_KW 8
+#endif
+
+template <int KW>
 __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_keys) {
     // Besides its destination every run gets its position among all runs
     // sorted by (key, tile): the key's list offset plus its rank among the
-    // key's runs by address (tile order).
+    // key's runs by address (tile order).  A wavefront takes 64 / KW keys at
+    // a time, KW lanes each; keys with up to 16 runs then take 16 lanes, four
+    // at a time, and longer ones the whole wavefront in turn.
+    static_assert(KW == 8 || KW == 16, "lanes per key");
+    constexpr int NG = 64 / KW;
     const int lane = threadIdx.x & 63;
-    const int grp = lane >> 4, sub = lane & 15;
+    const int grp = lane / KW, sub = lane % KW;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t k0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4; k0 < n_keys;
-         k0 += waves * 4) {
+    for (int64_t k0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * NG; k0 < n_keys;
+         k0 += waves * NG) {
         const int64_t key = k0 + grp;
         uint32_t len = 0, kb = 0, lo = 0;
         if (key < n_keys) {
@@ -559,15 +568,32 @@ __global__ __launch_bounds__(256) void k_step_place(RebinScratch sc, uint32_t n_
             kb = sc.key_base[key];
             lo = sc.list_off[key];
         }
-        if (__ballot(len != 0u) == 0) continue;   // four empty keys
+        if (__ballot(len != 0u) == 0) continue;   // all NG keys empty
         const uint32_t cap = sc.klist_cap;        // >= 16
-        if (len <= 16) place_sorted<16>(sc, sc.klist, (uint32_t)(key * cap), len, kb, sub, sc.run_pos, lo);
-        for (int g = 0; g < 4; ++g) {
+        if (len <= (uint32_t)KW) place_sorted<KW>(sc, sc.klist, (uint32_t)(key * cap), len, kb, sub, sc.run_pos, lo);
+        if (KW < 16) {
+            // keys with KW+1..16 runs: four at a time, 16 lanes each (the
+            // h-th such key, by lane, goes to lane group h)
+            uint64_t mid = __ballot(sub == 0 && len > (uint32_t)KW && len <= 16u);
+            const int h = lane >> 4, s16 = lane & 15;
+            while (mid) {
+                uint64_t m = mid;
+                for (int i = 0; i < h && m; ++i) m &= m - 1;
+                const int src = m ? __builtin_ctzll(m) : 0;
+                const uint32_t mlen = (uint32_t)__shfl((int)len, src, 64);
+                const uint32_t mkb = (uint32_t)__shfl((int)kb, src, 64);
+                const uint32_t mlo = (uint32_t)__shfl((int)lo, src, 64);
+                const int64_t mk = k0 + src / KW;
+                place_sorted<16>(sc, sc.klist, (uint32_t)(mk * cap), m ? mlen : 0u, mkb, s16, sc.run_pos, mlo);
+                for (int i = 0; i < 4 && mid; ++i) mid &= mid - 1;
+            }
+        }
+        for (int g = 0; g < NG; ++g) {
             const int64_t gk = k0 + g;
-            const uint32_t glen = (uint32_t)__shfl((int)len, g * 16, 64);
-            const uint32_t gkb = (uint32_t)__shfl((int)kb, g * 16, 64);
-            const uint32_t glo = (uint32_t)__shfl((int)lo, g * 16, 64);
-            if (glen <= 16) continue;
+            const uint32_t glen = (uint32_t)__shfl((int)len, g * KW, 64);
+            const uint32_t gkb = (uint32_t)__shfl((int)kb, g * KW, 64);
+            const uint32_t glo = (uint32_t)__shfl((int)lo, g * KW, 64);
+            if (glen <= (uint32_t)(KW < 16 ? 16 : KW)) continue;
             if (glen <= 64u && glen <= cap) {
                 place_sorted<64>(sc, sc.klist, (uint32_t)(gk * cap), glen, gkb, lane, sc.run_pos, glo);
                 continue;
@@ -662,7 +688,8 @@ void launch_step_middle(const pic_tree *t, int64_t n, int64_t n_bins, const Rebi
     PIC_LAUNCH("step_scan", k_step_scan, dim3((keys + SP_KEYS - 1) / SP_KEYS), dim3(SP_THREADS), 0, s, (uint32_t)keys,
                (uint32_t)n_bins, n, sc, new_start, t->dt.status);
     if (n > 0)
-        PIC_LAUNCH("step_place", k_step_place, dim3(grid_for(keys, 16, 1 << 16)), dim3(256), 0, s, sc, (uint32_t)keys);
+        PIC_LAUNCH("step_place", k_step_place<PIC_PLACE_KW>, dim3(grid_for(keys, 64 / PIC_PLACE_KW * 4, 1 << 16)),
+                   dim3(256), 0, s, sc, (uint32_t)keys);
 }
 
 }  // namespace pic

@@ -359,15 +359,16 @@ def test_fused_step_forms_match_oracle(name, scheme, knobs):
             pic.tune(k, v)
 
 
-@pytest.mark.parametrize("tiles", [80, 160])
+@pytest.mark.parametrize("tiles", [12, 80, 160])
 @pytest.mark.parametrize("step_fuse,group_match", [(1, 0), (0, 1), (0, 0)])
 @pytest.mark.parametrize("step_tile", [2048, 1024, 4096])
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, group_match, scheme, tiles):
     """Every tile sends particles to every bin of a 3x3 tree, so each key
-    collects about as many runs as there are tiles: 80 take the placement by
-    counting (more than a wavefront sorts), 160 overflow the direct list into
-    the linked rest.  The step still matches the oracle."""
+    collects about as many runs as there are tiles: 12 are placed by 16-lane
+    groups (more than the 8 lanes a key starts with; 2048-particle tiles),
+    80 by counting (more than a wavefront sorts), 160 overflow the direct
+    list into the linked rest.  The step still matches the oracle."""
     dev = _dev()
     saved = pic.tuning()
     try:
@@ -387,6 +388,15 @@ def test_fused_step_with_overfull_key_lists(step_tile, step_fuse, group_match, s
         st.step_fused(torch.tensor(E, device=dev), -0.9, 0.9, q_uniform=-1.0)
         r = oracle.step(o, xs, vs, E, -0.9, 0.9, start, scheme, None, -1.0)
         torch.cuda.synchronize()
+        # the case is the one meant: the most runs a key collects
+        old_bin = np.repeat(np.arange(len(start) - 1), np.diff(start))
+        new_bin = np.asarray(r["new_bin"], dtype=np.int64)
+        key = 2 * new_bin + (new_bin != old_bin)
+        pairs = np.unique(key * (n // step_tile + 1) + np.arange(n) // step_tile)
+        most = np.bincount(pairs // (n // step_tile + 1)).max()
+        if tiles == 12 and step_tile == 2048:
+            assert 8 < most <= 16
+        assert most <= (n + step_tile - 1) // step_tile
         assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
         assert np.array_equal(st.ids.cpu().numpy(), ids[r["perm"]])
         assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
