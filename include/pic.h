@@ -55,6 +55,7 @@ typedef int32_t pic_status;
 #define PIC_E_HIP 6        /* a HIP runtime call failed */
 #define PIC_E_RANGE 7      /* device: a position lay outside [0,1), or a bin outside the tree */
 #define PIC_E_STATE 8      /* call order violated (e.g. tree not uploaded) */
+#define PIC_E_MEMORY 9     /* host memory for a builder's tables could not be allocated */
 
 /* Particle storage schemes (paper Sec. 5.1 and Sec. 5.2). */
 #define PIC_PIT 0          /* particle in tree: bin = leaf covering x (Theorem 1) */
@@ -538,7 +539,9 @@ pic_status pic_leaf_counts(const pic_tree *tree, const pic_particles *p, uint64_
  * may be NULL with masks_cap 0 to ask for the size, and PIC_E_CAPACITY is
  * returned when masks_cap is below *masks_len.  One rule application per
  * call (an overfull leaf gains one level per call).  PIC_E_ARG for forests,
- * negative ppc or a max_level outside the tree limits.
+ * negative ppc or a max_level outside the tree limits; PIC_E_CAPACITY when
+ * the dense state of the deepest level the result can reach ((3^l)^d bytes)
+ * would exceed 16 GiB; PIC_E_MEMORY when the host heap is exhausted.
  */
 pic_status pic_tree_adapt(const pic_tree *tree, const int64_t *leaf_count, int64_t ppc, int32_t max_level,
                           uint8_t *masks, size_t masks_cap, size_t *masks_len, int32_t *new_max_level);

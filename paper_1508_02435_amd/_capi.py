@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PIC_LIBPIC") or os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_E_ARG, PIC_E_SCRATCH, PIC_E_CAPACITY, PIC_E_NONFINITE, PIC_E_TREE, PIC_E_HIP, PIC_E_RANGE, \
-    PIC_E_STATE = range(9)
+    PIC_E_STATE, PIC_E_MEMORY = range(10)
 PIT, PIDT = 0, 1
 F64, F32_OFFSET = 0, 1
 

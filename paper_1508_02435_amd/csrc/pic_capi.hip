@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -325,8 +326,8 @@ int64_t tune_get(const Tuning &g, const char *name) {
 
 extern "C" {
 
-pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level, const uint8_t *masks,
-                           pic_tree **out) {
+static pic_status tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level, const uint8_t *masks,
+                              pic_tree **out) {
     if (!out) return PIC_E_ARG;
     *out = nullptr;
     if ((dim != 2 && dim != 3) || n_inst < 1 || !max_level) return PIC_E_ARG;
@@ -337,8 +338,7 @@ pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level
         for (int l = 0; l < L; ++l) mask_total += (int64_t)pow3_u64(dim * l);
     }
     if (mask_total > 0 && !masks) return PIC_E_ARG;
-    pic_tree *t = new (std::nothrow) pic_tree();
-    if (!t) return PIC_E_ARG;
+    std::unique_ptr<pic_tree> t(new pic_tree());   // freed if a builder throws
     t->dim = dim;
     t->n_inst = n_inst;
     t->tune = g_tune;
@@ -347,21 +347,27 @@ pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level
     for (int i = 0; i < n_inst; ++i) {
         const int L = max_level[i];
         pic_status st = build_instance(dim, L, m, t->inst[i]);
-        if (st != PIC_OK) {
-            delete t;
-            return st;
-        }
+        if (st != PIC_OK) return st;
         for (int l = 0; l < L; ++l) m += pow3_u64(dim * l);
         t->all_regular &= t->inst[i].regular;
         t->max_level = std::max(t->max_level, L);
     }
-    pic_status st = assemble(t);
-    if (st != PIC_OK) {
-        delete t;
-        return st;
-    }
-    *out = t;
+    pic_status st = assemble(t.get());
+    if (st != PIC_OK) return st;
+    *out = t.release();
     return PIC_OK;
+}
+
+// The host-side builders allocate (tables, masks): no exception leaves the
+// C ABI, an exhausted host heap is a status.
+pic_status pic_tree_create(int32_t dim, int32_t n_inst, const int32_t *max_level, const uint8_t *masks,
+                           pic_tree **out) {
+    try {
+        return tree_create(dim, n_inst, max_level, masks, out);
+    } catch (const std::bad_alloc &) {
+        if (out) *out = nullptr;
+        return PIC_E_MEMORY;
+    }
 }
 
 void pic_tree_destroy(pic_tree *tree) { delete tree; }
@@ -482,6 +488,7 @@ const char *pic_status_string(pic_status s) {
         case PIC_E_HIP: return "HIP runtime error";
         case PIC_E_RANGE: return "coordinate outside the unit box or bin outside the tree";
         case PIC_E_STATE: return "tree not uploaded";
+        case PIC_E_MEMORY: return "host memory exhausted";
         default: return "unknown status";
     }
 }
@@ -558,7 +565,12 @@ pic_status pic_tree_adapt(const pic_tree *t, const int64_t *leaf_count, int64_t 
         if (leaf_count[r] < 0) return PIC_E_ARG;
     std::vector<uint8_t> m;
     int L = 0;
-    pic_status st = adapt_masks(t, leaf_count, ppc, max_level, m, L);
+    pic_status st;
+    try {
+        st = adapt_masks(t, leaf_count, ppc, max_level, m, L);
+    } catch (const std::bad_alloc &) {
+        return PIC_E_MEMORY;
+    }
     if (st != PIC_OK) return st;
     *masks_len = m.size();
     *new_max_level = L;

@@ -247,9 +247,13 @@ pic_status adapt_masks(const pic_tree *t, const int64_t *leaf_count, int64_t ppc
     const pic::HostInst &h = t->inst[0];
     const int d = t->dim, L = h.L;
     const int top = std::max(L, std::min(L + 1, max_level));   // deepest level the new tree can reach
-    int64_t p3[64];
+    // powers of 3 up to 3^39 < 2^63 (the tree limits keep d * top <= 36)
+    int64_t p3[40];
     p3[0] = 1;
-    for (int i = 1; i < 64; ++i) p3[i] = p3[i - 1] * 3;
+    for (int i = 1; i < 40; ++i) p3[i] = p3[i - 1] * 3;
+    if (d * top > 39) return PIC_E_ARG;
+    // the dense per-level states: refuse more than 16 GiB for the deepest
+    if (p3[d * top] > ((int64_t)1 << 34)) return PIC_E_CAPACITY;
     auto lex = [&](int l, const int64_t *a) {
         int64_t r = 0;
         for (int k = d - 1; k >= 0; --k) r = r * p3[l] + a[k];
