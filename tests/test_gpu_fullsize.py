@@ -9,7 +9,8 @@ per vertex (paper Sec. 5.1 Theorem 1, Sec. 5.2 Theorem 2, Sec. 3 step 1).
 
 At these sizes the step exercises what the small cases cannot: thousands of
 tiles, dozens of look-back scan blocks, keys collecting 60-130 runs, and
-(config 4) the 3D kernels at 34M particles.
+(config 4, PIT and PIDT) the 3D kernels at 34M particles in the
+4096-particle tiles that sparse 3D bins take.
 """
 import gc
 
@@ -65,7 +66,7 @@ def _oracle_langmuir(o, wl, scheme, steps):
 
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("name,scheme", [("config2", pic.PIT), ("config2", pic.PIDT), ("config3", pic.PIT),
-                                         ("config4", pic.PIT)])
+                                         ("config4", pic.PIT), ("config4", pic.PIDT)])
 def test_benchmark_step_matches_oracle_at_full_size(name, scheme):
     """Configs 2 and 4 start from the oracle's state after the benchmark's
     warmup of self-consistent Langmuir steps, with the field of the next
