@@ -72,11 +72,13 @@ def algorithmic_bytes_f32(dim: int, per_particle_q: bool, stored: bool = False):
     }
 
 
-def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False):
+def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False, emit_deposit: bool = False):
     """Bytes each kernel must move per particle (FP64 form).  "calls" is the
     three-call path (gather_push, rebin, deposit); "fused" is pic_step (key,
     group and emit passes, then the deposit); `stored`: the key pass writes
-    the pushed state back (knob key_stores)."""
+    the pushed state back (knob key_stores); `emit_deposit`: the writing pass
+    deposits while the positions are in LDS, so the deposit reads no
+    positions (its per-run partials, a few per tile, are not counted)."""
     s_push = 2 * 8 * dim                   # x, v
     q = 8 if per_particle_q else 0
     s_rec = s_push + q                     # a full record moved by a rebin
@@ -91,7 +93,7 @@ def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False):
         "step_emit": s_push + 4 + s_rec + q,   # x, v, run index | rank (and q) read, the record written
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
     }
-    ab["fused"] = ab["step_key"] + ab["step_group"] + ab["step_emit"] + s_dep
+    ab["fused"] = ab["step_key"] + ab["step_group"] + ab["step_emit"] + (0 if emit_deposit else s_dep)
     return ab
 
 
@@ -609,10 +611,16 @@ def main():
         return st
 
     accuracy = fp32_accuracy(pic, torch, tree, scheme, wl, x0_host, v0_host, fields[0], dev) if f32 else None
-    ks = pic.tuning(tree)["key_stores"]
+    knobs = pic.tuning(tree)
+    ks, ed = knobs["key_stores"], knobs["emit_deposit"]
     stored = args.path == "fused" and (ks == 1 or (ks == 2 and f32 and wl.dim == 3))
+    # the writing pass deposits (the library's rule: FP64 fused step, 2D
+    # regular single tree, uniform charge, tiles of at most 2048)
+    emit_dep = (args.path == "fused" and not f32 and wl.dim == 2 and tree.regular and tree.n_inst == 1 and
+                wl.q is None and knobs["step_tile"] in (0, 1024, 2048) and
+                (ed == 1 or (ed == 2 and scheme == pic.PIT)))
     ab = algorithmic_bytes_f32(wl.dim, wl.q is not None, stored) if f32 else \
-        algorithmic_bytes(wl.dim, wl.q is not None, stored)
+        algorithmic_bytes(wl.dim, wl.q is not None, stored, emit_dep)
     lib = pic.lib()
     st = fresh()
     step = st.step_fused if args.path == "fused" else st.step

@@ -444,9 +444,9 @@ pic_status pic_profile_only(const char *name);
  *   "emit_deposit"  1 = for 2D single trees whose instances are regular and a uniform
  *                   charge, pic_step's writing pass sums each run's weights while
  *                   the run is in LDS and the deposit only adds runs per bin; 0 = the
- *                   deposit reads the re-binned positions again (default 0: the
- *                   second read leaves the positions in the last-level cache for the
- *                   next step's key pass, which makes up for it);
+ *                   deposit reads the re-binned positions again; 2 = 1 for PIT and
+ *                   0 for PIDT, whose nine-weight stencil costs the writing pass
+ *                   more than the second read (default 2);
  *   "regular_tables" (process default only) 1 = trees created afterwards get Peano
  *                   rank tables for their regular instances (up to 2^21 cells per
  *                   level), which the arithmetic kernels and the FP32 form use;

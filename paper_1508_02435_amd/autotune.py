@@ -25,7 +25,7 @@ SPACES = {
     # per lane group (the deposit's bucket), the writing-pass deposit, the
     # stored push, the ranking form
     "fused_f64": {"step_tile": (2048, 1024, 4096), "emit_threads": (1024, 512), "deposit_lanes": (64, 32, 16),
-                  "deposit_bpw": (1, 2), "emit_deposit": (0, 1), "key_stores": (2, 1), "group_match": (0, 1)},
+                  "deposit_bpw": (1, 2), "emit_deposit": (2, 0, 1), "key_stores": (2, 1), "group_match": (0, 1)},
     "calls_f64": {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1),
                   "scatter_group": (4, 2, 1), "deposit_lanes": (64, 32, 16)},
     "f32": {"xcd_tiles": (1, 0), "key_stores": (2, 1, 0), "group_match": (0, 1)},

@@ -292,7 +292,7 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
         if (!one_of({0, 1})) return false;
         g.group_match = (int)value;
     } else if (k == "emit_deposit") {
-        if (!one_of({0, 1})) return false;
+        if (!one_of({0, 1, 2})) return false;
         g.emit_deposit = (int)value;
     } else {
         return false;

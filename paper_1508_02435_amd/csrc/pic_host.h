@@ -54,7 +54,8 @@ struct Tuning {
     int key_stores = 2;     // fused step: the key pass stores the pushed state in place and the writing pass
                             // moves it: 1 always, 0 never, 2 for the FP32 form of 3D trees
     int group_match = 0;    // fused step's ranking pass: 1 = by wavefront key matching, 0 = by LDS tags and masks
-    int emit_deposit = 0;   // fused step, 2D regular single trees, uniform charge: 1 = the writing pass deposits
+    int emit_deposit = 2;   // fused step, 2D regular single trees, uniform charge: 1 = the writing pass deposits,
+                            // 2 = it does for PIT only
     int deposit_bpw = 1;    // bins a deposit lane group takes one after the other: 1 or 2
     int deposit_batch = 64; // particles a deposit lane group takes per round: 64 or 256
     int regular_tables = 1; // build Peano rank tables for regular instances (read when a tree is created)

@@ -515,7 +515,10 @@ hipError_t launch_step(const pic_tree *t, int scheme, pic_particles *in, const i
     a.old_start = old_start;
     a.n_bins = (uint32_t)n_bins;
     a.stats = stats;
-    a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && t->tune.emit_deposit && tile <= 2048;
+    // the writing pass deposits: on request, or by default for PIT (for
+    // PIDT its nine-slot stencil costs the writing pass more than it saves)
+    const bool dep_knob = t->tune.emit_deposit == 1 || (t->tune.emit_deposit == 2 && scheme == PIC_PIT);
+    a.deposit = t->dim == 2 && t->reg_kernels && t->n_inst == 1 && q_col < 0 && dep_knob && tile <= 2048;
     a.flops = 0;
     a.ipt = ipt;
     if (t->dim == 2) {

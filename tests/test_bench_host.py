@@ -36,6 +36,14 @@ def test_fused_bytes_per_pass_form():
             assert ab["fused"] < ab["calls"]
 
 
+def test_fused_bytes_with_the_writing_pass_deposit():
+    """When the writing pass deposits, the deposit reads no positions: the 2D
+    step moves 112 B (key 36, group 8, writing 68)."""
+    ab = bench.algorithmic_bytes(2, False, emit_deposit=True)
+    assert ab["fused"] == 112
+    assert ab["step_emit"] == bench.algorithmic_bytes(2, False)["step_emit"]
+
+
 def test_more_than_one_gpu_is_refused():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)
