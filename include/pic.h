@@ -417,7 +417,8 @@ pic_status pic_profile_only(const char *name);
  *                   the tile (default 0);
  *   "scatter_nt"    1 = non-temporal stores for the re-binned records (default 0);
  *   "scatter_group" columns a scatter thread holds in registers, 1, 2 or 4 (default 4);
- *   "deposit_lanes" lanes that reduce one bin in the deposit, 16, 32 or 64 (default 64);
+ *   "deposit_lanes" lanes that reduce one bin in the FP64 deposit, 16, 32 or 64, or
+ *                   0 = 32 for 3D trees and 64 for 2D ones (default 0);
  *   "deposit_bpw"   bins such a lane group takes one after the other, 1 or 2 (default 1);
  *   "deposit_batch" particles a bin's lane group takes per round in the FP64
  *                   deposit, 64 or 256 (default 64; the FP32 deposit takes 256);

@@ -259,7 +259,7 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
         if (!one_of({1, 2, 4})) return false;
         g.scatter_group = (int)value;
     } else if (k == "deposit_lanes") {
-        if (!one_of({16, 32, 64})) return false;
+        if (!one_of({0, 16, 32, 64})) return false;
         g.deposit_lanes = (int)value;
     } else if (k == "regular_tables") {
         if (!one_of({0, 1})) return false;

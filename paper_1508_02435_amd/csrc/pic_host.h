@@ -45,7 +45,7 @@ struct Tuning {
     int scatter_mode = 0;   // 0: LDS-staged scatter, 1: direct gather from the tile
     int scatter_nt = 0;     // 1: non-temporal stores of the re-binned records
     int scatter_group = 4;  // columns a scatter thread holds in registers at once: 1, 2 or 4
-    int deposit_lanes = 64; // lanes per bin in the deposit: 16, 32 or 64
+    int deposit_lanes = 0;  // lanes per bin in the deposit: 16, 32 or 64; 0 = by dimension (deposit_lanes_of)
     int step_ipt = 0;       // particles per thread in a fused-step tile: 4, 8 or 16 (1024, 2048, 4096 tile);
                             // 0 = by dimension (step_ipt_of)
     int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
@@ -95,6 +95,14 @@ namespace pic {
 // sources (fewer, longer runs: fewer partly written cache lines in the
 // writing pass).  Fuller bins already give long runs and every other tree
 // takes 2048, which keeps more blocks resident.
+// Lanes per bin of the FP64 deposit.  By default 32 for 3D trees (two bins
+// per wavefront: on the 3D plasma the per-bin pass takes 0.28 instead of
+// 0.34 ms for PIT and 0.66 instead of 0.82 ms for PIDT) and 64 for 2D ones,
+// where 32 is slower (adaptive 2D: 0.124 instead of 0.109 ms).
+inline int deposit_lanes_of(const pic_tree *t) {
+    return t->tune.deposit_lanes ? t->tune.deposit_lanes : (t->dim == 3 ? 32 : 64);
+}
+
 inline int step_ipt_of(const pic_tree *t, int64_t n, int64_t n_bins) {
     if (t->tune.step_ipt) return t->tune.step_ipt;
     return t->dim == 3 && n <= 256 * n_bins ? 16 : 8;

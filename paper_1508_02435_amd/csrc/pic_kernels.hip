@@ -352,8 +352,8 @@ size_t deposit_scratch_bytes(const pic_tree *t, int scheme) {
 
 #define PIC_DISPATCH_DEP(D, SCH, REG)                                                                         \
     do {                                                                                                     \
-        if (t->tune.deposit_lanes == 16) PIC_DEP_BINS(D, SCH, REG, 16);                                       \
-        else if (t->tune.deposit_lanes == 32) PIC_DEP_BINS(D, SCH, REG, 32);                                  \
+        if (deposit_lanes_of(t) == 16) PIC_DEP_BINS(D, SCH, REG, 16);                                         \
+        else if (deposit_lanes_of(t) == 32) PIC_DEP_BINS(D, SCH, REG, 32);                                    \
         else PIC_DEP_BINS(D, SCH, REG, 64);                                                                  \
         PIC_LAUNCH("deposit_vertices", (k_deposit_vertices<D, SCH, REG>), dim3(grid_for(n_vtx, 256, 1 << 16)), dim3(256), \
                            0, s, t->dt, t->inst0, partial, n_vtx, q ? 1 : 0, q_uniform, rho);                 \
