@@ -168,6 +168,34 @@ def test_edge_sizes_and_positions(n, kind, scheme):
     assert t.status_sync() == 0
 
 
+@pytest.mark.parametrize("n", [0, 1, 63, 4095, 4096, 4097, 3 * 4096 + 17])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_fused_step_edge_sizes_with_default_launch_shape(n, dim, scheme):
+    """pic_step with the default knobs on regular trees, at empty, tiny and
+    tile-boundary sizes: in 3D (few particles per bin) the 4096-particle
+    tiles, in 2D the 2048-particle tiles and, for PIT, the writing-pass
+    deposit.  Offsets, state and order bit for bit; charge within 1e-12."""
+    dev = _dev()
+    rng = np.random.default_rng(n + 11 * dim + scheme)
+    spec = W.regular_tree(dim, 2 if dim == 3 else 3)
+    o = oracle.OracleTree(spec)
+    t = _tree(spec)
+    x, v = _synthetic(n, dim, rng, "uniform")
+    st = pic.Stepper(t, scheme, x, v, ids=np.arange(n, dtype=np.int64), device=dev)
+    st.initial_sort()
+    xs, vs, _, start, ids = oracle.initial_sort(o, x, v, None, scheme)
+    E = W.random_field(rng, dim, o.n_vertices, 0.3)
+    st.step_fused(torch.tensor(E, dtype=torch.float64, device=dev), -0.7, 0.7, q_uniform=-1.0)
+    r = oracle.step(o, xs, vs, E, -0.7, 0.7, start, scheme, None, -1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.start.cpu().numpy(), r["bin_start"])
+    assert np.array_equal(st.ids.cpu().numpy(), ids[r["perm"]])
+    assert np.array_equal(st.x.cpu().numpy(), r["x"]) and np.array_equal(st.v.cpu().numpy(), r["v"])
+    _check_rho(st.rho.cpu().numpy(), r["rho"])
+    assert t.status_sync() == 0
+
+
 def test_nonfinite_and_out_of_box_are_flagged_not_fatal():
     dev = _dev()
     spec = W.regular_tree(2, 3)
