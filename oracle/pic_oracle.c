@@ -33,6 +33,11 @@
  *     order, then particles that arrived, in their old order;
  *   - leapfrog with v at half steps; x wraps periodically into [0,1).
  *
+ * Parity unpinned (fixed by these readings, not by anything the paper or the
+ * mathematics determines): the PIDT owner's tie-break at coarse-fine
+ * interfaces, the order inside a bin, the exact PIDT key on adaptive trees,
+ * and the PIDT lift count beyond the mechanism the tests check.
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
  */
 #include <math.h>
