@@ -622,6 +622,15 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int on) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// The same chunks walked backwards: an XCD starts at the end of its chunk,
+// where the previous pass over the same chunks wrote last (still in its L2
+// and in the memory-side cache).
+__device__ __forceinline__ int64_t xcd_tile_rev(int64_t b, int64_t tiles) {
+    const int64_t x = b & 7, k = b >> 3, q = tiles >> 3, r = tiles & 7;
+    const int64_t size = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + (size - 1 - k);
+}
+
 // ----------------------------------------------------------------- deposit
 
 // Sum over groups of G consecutive lanes (butterfly inside the group, fixed
