@@ -296,7 +296,10 @@ __global__ __launch_bounds__(256, MULTI ? 4 : 6) void k_step_key_f32(DevTree t, 
                                                       uint32_t n_bins, const uint32_t *tile_bin, int tile,
                                                       uint32_t *key_out, const uint32_t *wave_bin, int store) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    // as the FP64 key pass: the writing pass's XCD chunks walked backwards
+    const bool one_pass = stride >= n;
+    const int64_t b0 = one_pass ? xcd_tile_rev(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    for (int64_t p = b0 * blockDim.x + threadIdx.x; p < n; p += one_pass ? n : stride) {
         int ii = 0;
         if (MULTI) ii = inst_of(inst_start, t.n_inst, p);
         const DevInst &in = MULTI ? t.inst[ii] : in0;
