@@ -750,6 +750,9 @@ def main():
                    "knobs": pic.tuning(tree)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        # per-launch averages from a second run of the same steps with every
+        # launch bracketed by events and the re-bin statistics on (rebin_stats
+        # is that run's statistics kernel, not part of the timed step)
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in per_kernel.items()},
         "rebin_stats": rebin_stats,
         "stream_benchmark": stream,
