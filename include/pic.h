@@ -431,8 +431,10 @@ pic_status pic_profile_only(const char *name);
  *   "xcd_tiles"     1 = the tiles of pic_step's writing pass are dealt to the chip's
  *                   8 XCDs in contiguous chunks, 0 = in block order (default 1);
  *   "emit_threads"  threads per block of that pass, 512 or 1024 (default 1024);
- *   "step_fuse"     1 = pic_step's key pass and tile ranking run as one kernel, 0 = as
- *                   a key pass that writes the keys and a ranking pass (default 0);
+ *   "step_fuse"     1 = pic_step's FP64 key pass and tile ranking run as one kernel
+ *                   (ranking by matching), 0 = as a key pass that writes the keys and
+ *                   a ranking pass; 2 = 1 for PIT on 2D single trees whose instances
+ *                   are regular, unless key_stores is 1, else 0 (default 2);
  *   "key_stores"    1 = pic_step's key pass stores the pushed state back into `in`
  *                   (x, v or off, u, in the old order) and the writing pass only
  *                   moves it; 0 = the writing pass pushes again and `in` stays

@@ -185,7 +185,7 @@ def _check_inst(tree, inst_start):
 
 TUNING_KNOBS = {"rebin_tile": (2048, 4096), "rebin_radix": (4, 5), "scatter_mode": (0, 1), "scatter_nt": (0, 1),
                 "scatter_group": (1, 2, 4), "deposit_lanes": (0, 16, 32, 64), "step_tile": (0, 2048, 1024, 4096),
-                "xcd_tiles": (1, 0), "emit_threads": (1024, 512), "deposit_bpw": (1, 2), "deposit_batch": (64, 256), "step_fuse": (0, 1), "emit_deposit": (2, 0, 1),
+                "xcd_tiles": (1, 0), "emit_threads": (1024, 512), "deposit_bpw": (1, 2), "deposit_batch": (64, 256), "step_fuse": (2, 0, 1), "emit_deposit": (2, 0, 1),
                 "group_match": (0, 1), "key_stores": (2, 0, 1),
                 "regular_tables": (1, 0)}
 PROCESS_ONLY = ("regular_tables",)   # read when a tree is created; not a knob of a tree

@@ -283,7 +283,7 @@ bool tune_set(Tuning &g, const char *name, int64_t value) {
         if (!one_of({512, 1024})) return false;
         g.emit_threads = (int)value;
     } else if (k == "step_fuse") {
-        if (!one_of({0, 1})) return false;
+        if (!one_of({0, 1, 2})) return false;
         g.step_fuse = (int)value;
     } else if (k == "key_stores") {
         if (!one_of({0, 1, 2})) return false;

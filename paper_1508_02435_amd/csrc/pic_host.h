@@ -50,7 +50,8 @@ struct Tuning {
                             // 0 = by dimension (step_ipt_of)
     int xcd_tiles = 1;      // 1 = tiles dealt to the 8 XCDs in contiguous chunks, 0 = block order
     int emit_threads = 1024; // threads per emit block: 512 or 1024
-    int step_fuse = 0;      // fused step: 1 = key pass and tile ranking in one kernel, 0 = two kernels
+    int step_fuse = 2;      // fused step: 1 = key pass and tile ranking in one kernel, 0 = two kernels,
+                            // 2 = one kernel for 2D regular single trees with PIT
     int key_stores = 2;     // fused step: the key pass stores the pushed state in place and the writing pass
                             // moves it: 1 always, 0 never, 2 for the FP32 form of 3D trees
     int group_match = 0;    // fused step's ranking pass: 1 = by wavefront key matching, 0 = by LDS tags and masks

@@ -439,8 +439,11 @@ static void launch_step_passes(const pic_tree *t, const StepArgs &a, const Rebin
                                int64_t *new_start, hipStream_t s) {
     const int64_t tiles = (a.n + TILE - 1) / TILE;
     // the fused key+rank kernel pushes only; a streaming step takes the key
-    // and ranking passes
-    const bool fuse = t->tune.step_fuse && MOVE == MOVE_PUSH && TILE <= 2048;
+    // and ranking passes.  By default (step_fuse 2) 2D regular single trees
+    // take it for PIT, unless the key pass is to store the pushed state.
+    const bool fuse_auto = D == 2 && REG && !MULTI && SCH == PIC_PIT && t->tune.key_stores != 1;
+    const bool fuse = (t->tune.step_fuse == 1 || (t->tune.step_fuse == 2 && fuse_auto)) && MOVE == MOVE_PUSH &&
+                      TILE <= 2048;
     // the key pass stores the moved state (the fused key+rank kernel does not)
     const bool stored = t->tune.key_stores == 1 && !fuse;
     if (a.n > 0 && fuse) {
