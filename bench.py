@@ -72,13 +72,16 @@ def algorithmic_bytes_f32(dim: int, per_particle_q: bool, stored: bool = False):
     }
 
 
-def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False, emit_deposit: bool = False):
+def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False, emit_deposit: bool = False,
+                      fused_rank: bool = False):
     """Bytes each kernel must move per particle (FP64 form).  "calls" is the
     three-call path (gather_push, rebin, deposit); "fused" is pic_step (key,
     group and emit passes, then the deposit); `stored`: the key pass writes
     the pushed state back (knob key_stores); `emit_deposit`: the writing pass
     deposits while the positions are in LDS, so the deposit reads no
-    positions (its per-run partials, a few per tile, are not counted)."""
+    positions (its per-run partials, a few per tile, are not counted);
+    `fused_rank`: the key pass and the ranking are one kernel (knob
+    step_fuse), which writes no keys."""
     s_push = 2 * 8 * dim                   # x, v
     q = 8 if per_particle_q else 0
     s_rec = s_push + q                     # a full record moved by a rebin
@@ -93,7 +96,9 @@ def algorithmic_bytes(dim: int, per_particle_q: bool, stored: bool = False, emit
         "step_emit": s_push + 4 + s_rec + q,   # x, v, run index | rank (and q) read, the record written
         "calls": 2 * s_push + 2 * s_rec + s_dep + 8,
     }
-    ab["fused"] = ab["step_key"] + ab["step_group"] + ab["step_emit"] + (0 if emit_deposit else s_dep)
+    ab["step_keyrank"] = s_push + 4                 # x, v read, run index | rank written
+    first = ab["step_keyrank"] if fused_rank else ab["step_key"] + ab["step_group"]
+    ab["fused"] = first + ab["step_emit"] + (0 if emit_deposit else s_dep)
     return ab
 
 
@@ -619,8 +624,13 @@ def main():
     emit_dep = (args.path == "fused" and not f32 and wl.dim == 2 and tree.regular and tree.n_inst == 1 and
                 wl.q is None and knobs["step_tile"] in (0, 1024, 2048) and
                 (ed == 1 or (ed == 2 and scheme == pic.PIT)))
+    # the key pass and the ranking as one kernel (the library's rule)
+    sf = knobs["step_fuse"]
+    fuse_auto = wl.dim == 2 and tree.regular and tree.n_inst == 1 and scheme == pic.PIT and ks != 1
+    fused_rank = (args.path == "fused" and not f32 and knobs["step_tile"] in (0, 1024, 2048) and
+                  (sf == 1 or (sf == 2 and fuse_auto)))
     ab = algorithmic_bytes_f32(wl.dim, wl.q is not None, stored) if f32 else \
-        algorithmic_bytes(wl.dim, wl.q is not None, stored, emit_dep)
+        algorithmic_bytes(wl.dim, wl.q is not None, stored, emit_dep, fused_rank)
     lib = pic.lib()
     st = fresh()
     step = st.step_fused if args.path == "fused" else st.step

@@ -42,6 +42,8 @@ def test_fused_bytes_with_the_writing_pass_deposit():
     ab = bench.algorithmic_bytes(2, False, emit_deposit=True)
     assert ab["fused"] == 112
     assert ab["step_emit"] == bench.algorithmic_bytes(2, False)["step_emit"]
+    # with the key pass and the ranking in one kernel no keys are written or read
+    assert bench.algorithmic_bytes(2, False, emit_deposit=True, fused_rank=True)["fused"] == 104
 
 
 def test_more_than_one_gpu_is_refused():
