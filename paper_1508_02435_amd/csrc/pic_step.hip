@@ -28,10 +28,13 @@ __global__ __launch_bounds__(256, 5) void k_step_key(DevTree t, DevInst in0, F64
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += stride) zero[i] = 0u;
     // one block per 256 particles when the grid covers the set: the blocks
-    // walk the writing pass's XCD chunks backwards (xcd_tile_rev).  Not for
-    // adaptive 2D trees, whose key pass (a descent per particle) runs faster
-    // forwards (0.181 instead of 0.196 ms on the adaptive 2D workload).
-    const bool one_pass = (D == 3 || REG) && stride >= n;
+    // of the leapfrog push walk the writing pass's XCD chunks backwards
+    // (xcd_tile_rev).  Not for adaptive 2D trees, whose key pass (a descent
+    // per particle) runs faster forwards (0.181 instead of 0.196 ms on the
+    // adaptive 2D workload), nor for free streaming, which runs faster
+    // forwards too (1.23 instead of 2.15 ms with 4096 artificial flops per
+    // move, 0.108 instead of 0.117 ms in 3D).
+    const bool one_pass = MOVE == MOVE_PUSH && (D == 3 || REG) && stride >= n;
     const int64_t b0 = one_pass ? xcd_tile_rev(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     for (int64_t p = b0 * blockDim.x + threadIdx.x; p < n; p += one_pass ? n : stride) {
         uint32_t bad = 0;
