@@ -409,8 +409,13 @@ __device__ __forceinline__ uint32_t stream_one(const DevTree &t, const DevInst &
 #pragma unroll
     for (int k = 0; k < D; ++k) stream_axis<BC>(xv[k], vv[k], dt, bad);
     if (flops > 0) {
+        // unrolled: one taken branch per sixteen operations instead of per
+        // two, so a wave waits on the chain's own latency and a few resident
+        // waves keep the VALU busy
         double a = xv[0];
-        for (int f = 0; f < flops / 2; ++f) a = __dadd_rn(__dmul_rn(a, 0.5), 0.25);
+        const int pairs = flops / 2;
+#pragma unroll 8
+        for (int f = 0; f < pairs; ++f) a = __dadd_rn(__dmul_rn(a, 0.5), 0.25);
         if (a < -1.0) bad |= PIC_DEV_RANGE;
     }
     if (!KEY) return 0u;

@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256, 5) void k_step_key(DevTree t, DevInst in0, F64
     // (xcd_tile_rev).  Not for adaptive 2D trees, whose key pass (a descent
     // per particle) runs faster forwards (0.181 instead of 0.196 ms on the
     // adaptive 2D workload), nor for free streaming, which runs faster
-    // forwards too (1.23 instead of 2.15 ms with 4096 artificial flops per
-    // move, 0.108 instead of 0.117 ms in 3D).
+    // forwards too (0.108 instead of 0.117 ms in 3D; with 4096 artificial
+    // flops per move, before that chain was unrolled, 1.23 instead of 2.15).
     const bool one_pass = MOVE == MOVE_PUSH && (D == 3 || REG) && stride >= n;
     const int64_t b0 = one_pass ? xcd_tile_rev(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     for (int64_t p = b0 * blockDim.x + threadIdx.x; p < n; p += one_pass ? n : stride) {

@@ -33,7 +33,7 @@ def _paper_particles(rng, dim, n, box=1.0):
     return x, d * rng.random(n)
 
 
-@pytest.mark.parametrize("flops", [0, 256])
+@pytest.mark.parametrize("flops", [0, 250])
 @pytest.mark.parametrize("boundary", [pic._capi.PERIODIC, pic._capi.REFLECTING])
 @pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("name", sorted(TREES))
@@ -171,7 +171,7 @@ def test_vmax_matches_oracle(name, scheme):
 
 
 @pytest.mark.parametrize("tile", [2048, 1024, 4096])
-@pytest.mark.parametrize("flops", [0, 64])
+@pytest.mark.parametrize("flops", [0, 46])
 @pytest.mark.parametrize("boundary", [pic._capi.PERIODIC, pic._capi.REFLECTING])
 @pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("name", sorted(TREES))
